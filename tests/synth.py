@@ -1,0 +1,40 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU parity tests.
+
+Holds no HOTRG arithmetic: random tensors with the Z2 structure of the h = 0
+flow (entries whose bond parities sum to odd are zero, parity of bond index i
+is i mod 2), random isometries (orthonormal columns), and index samples.
+"""
+import numpy as np
+
+SEED = 1906060
+
+
+def z2_tensor(dims, seed=SEED, odd=False, dtype=np.float64):
+    """Gaussian rank-2d tensor with legs (D0, D0, D1, D1, ..), Frobenius norm 1.
+
+    odd=False keeps the entries with an even parity sum (a pure tensor),
+    odd=True the odd ones (a one-impurity tensor)."""
+    shape = []
+    for D in dims:
+        shape += [D, D]
+    rng = np.random.default_rng(seed)
+    T = rng.standard_normal(shape)
+    par = np.indices(shape).sum(axis=0) % 2
+    T[par != (1 if odd else 0)] = 0.0
+    T /= np.linalg.norm(T)
+    return T.astype(dtype)
+
+
+def isometry(n, k, seed=SEED + 1):
+    """n x k matrix with orthonormal columns (QR of a Gaussian matrix)."""
+    rng = np.random.default_rng(seed)
+    q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    return np.ascontiguousarray(q)
+
+
+def sample_indices(shape, count, seed=SEED + 2):
+    """`count` distinct multi-indices of `shape`, sorted, as a list of tuples."""
+    rng = np.random.default_rng(seed)
+    total = int(np.prod(shape))
+    flat = np.sort(rng.choice(total, size=min(count, total), replace=False))
+    return [tuple(int(v) for v in np.unravel_index(f, shape)) for f in flat]
