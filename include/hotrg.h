@@ -1,0 +1,149 @@
+/*
+ * hotrg.h -- C ABI of the MI355X (gfx950) HOTRG library for the 4D Ising model.
+ *
+ * Method: Akiyama, Kuramashi, Yamashita, Yoshimura, "Phase transition of
+ * four-dimensional Ising model with higher-order tensor renormalization
+ * group" (arXiv:1906.06060), Sec. 2.  The library holds one coarse-graining
+ * state (T, and the impure tensors S_m, S_e) in device memory and advances it
+ * one direction at a time.
+ *
+ * Conventions shared by every call
+ *   - Tensors are rank 8 with legs (x, x', y, y', z, z', t, t') in row-major
+ *     order (leg x outermost, t' contiguous), FP64.  Leg q is the backward,
+ *     q' the forward bond of axis q; backward and forward legs of one axis
+ *     share a dimension D_q.  Axis ids: 0 = x, 1 = y, 2 = z, 3 = t.
+ *   - All device work is enqueued on the stream given in hotrg_config
+ *     (a hipStream_t; NULL = the default stream).  Calls that return host
+ *     values synchronise that stream before returning.
+ *   - Every call returns an int status (HOTRG_OK = 0 or a negative code);
+ *     no C++ exception crosses the ABI.  hotrg_last_error() gives a
+ *     thread-local message for the last failure on the calling thread.
+ *   - Ownership: the context owns every device buffer it allocates
+ *     (hipMalloc); hotrg_free releases them.  Host pointers passed in are
+ *     only read (or written, for outputs) during the call.
+ *   - After HOTRG_EDEVICE or HOTRG_ENUMERIC the context is marked failed:
+ *     every later call except hotrg_free returns HOTRG_ESTATE.
+ */
+#ifndef HOTRG_H
+#define HOTRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HOTRG_OK = 0,
+    HOTRG_EINVAL = -1,   /* bad argument (range, NULL pointer, axis not in 0..3) */
+    HOTRG_ENOMEM = -2,   /* device allocation failed or the plan exceeds the budget */
+    HOTRG_EDEVICE = -3,  /* a HIP call failed */
+    HOTRG_ESTATE = -4,   /* call not valid in the current state */
+    HOTRG_ENUMERIC = -5  /* norm or trace not finite and positive (Tr <= 0 signals breakdown) */
+};
+
+enum { HOTRG_FP64 = 0, HOTRG_BF16X3 = 1 };
+
+typedef struct hotrg_ctx hotrg_ctx;
+
+typedef struct {
+    int precision;        /* HOTRG_FP64 or HOTRG_BF16X3 (split bf16 hi/lo, 3 products,
+                             FP32 accumulation in chunks, FP64 across chunks) */
+    int impurities;       /* 1: carry S_m (Eq. (2.11)) and S_e (Eq. (2.7)); 0: pure T only */
+    int keep_checkpoints; /* 1: keep T^(k-1), U's and c_k of every step (needed by hotrg_backward) */
+    int mixed_from_step;  /* first step (1-based) whose contraction uses the mixed path; 0 -> 4 */
+    double tau_deg;       /* gap threshold of the degenerate-cut rule; 0 -> 1e-12 */
+    void *stream;         /* hipStream_t; NULL = default stream */
+    size_t slice_budget;  /* bytes for the contraction operand slices; 0 -> automatic */
+} hotrg_config;
+
+/* Set up the one-site state of Eqs. (2.2) and (2.6) with bond dimension 2:
+ *   W = [[sqrt cosh b, sqrt sinh b], [sqrt cosh b, -sqrt sinh b]] (W W^T = bond matrix, Eq. (2.1)),
+ *   T^(0) = sum_s e^{b h s} prod_8 W[s, i],  S^(0) = same with an extra factor s,
+ * normalised by c_0 = |T^(0)|_F.  beta >= 0 (ferromagnetic), h finite, dcut >= 1.
+ * hotrg_init uses the defaults (FP64, impurities on, no checkpoints). */
+int hotrg_init(double beta, double h, int dcut, hotrg_ctx **out);
+int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotrg_ctx **out);
+
+/* One coarse-graining step along `axis` (Sec. 2; Eqs. (2.8)-(2.9) in 4D):
+ * squeezed environments of the merged transverse legs (HOSVD, FP64), FP64
+ * eigendecomposition on the device, truncation to k <= dcut, then
+ * T' = U U U . T . T . U U U contracted on the MFMA cores, and S_m' = U.S_m.T.U,
+ * S_e' = U.S_e.S_e.U on the first step and U.S_e.T.U afterwards.  All three
+ * are divided by c_n = |T'|_F; ln Z bookkeeping is updated in FP64. */
+int hotrg_step(hotrg_ctx *ctx, int axis);
+
+/* ln Z / N after n steps (N = 2^n sites, Eqs. (2.3)-(2.5)):
+ *   lnZ/N = sum_{k<=n} 2^-k ln c_k + 2^-n ln Tr T^(n). */
+int hotrg_lnZ(hotrg_ctx *ctx, double *lnz_per_site);
+
+typedef struct {
+    int n;              /* steps taken */
+    int dims[4];        /* current bond dimensions (D_x, D_y, D_z, D_t) */
+    double lnz_per_site;
+    double trace;       /* Tr T^(n) of the normalised tensor, Eq. (2.5) */
+    double m_imp;       /* <sigma> = Tr S_m / Tr T, Eq. (2.12) */
+    double nn_imp;      /* <sigma_i sigma_j> = Tr S_e / Tr T, Eq. (2.10); pair along the first step's axis */
+    double e_imp;       /* -(1/N) dlnZ/dbeta estimate: -4 nn_imp - h m_imp */
+    double X;           /* (Tr A)^2 / Tr A^2 along the last step's axis, Eqs. (3.2)-(3.3) */
+    int last_axis;      /* axis of the last step, -1 before the first */
+    int last_side[4];   /* per transverse axis: 0 backward / 1 forward env chosen; -1 untruncated or mu */
+    int last_k[4];      /* kept dimension per axis in the last step */
+    double last_eps[4]; /* discarded weight of the chosen side */
+    double min_cut_gap; /* smallest (lam_k - lam_k+1)/lam_1 at a cut in the last step (inf if none) */
+    int flagged;        /* 1 if a cut stayed inside a degenerate multiplet (no gap above tau) */
+    double last_cn;     /* c_n of the last step (Frobenius norm before normalisation) */
+    size_t device_bytes;/* device memory held by the context */
+} hotrg_obs;
+
+/* Observables at the current step (impurity ratios need impurities = 1).
+ * Unlike hotrg_lnZ this does not fail on Tr T <= 0 (possible for a state set
+ * with hotrg_set_state): lnz_per_site is then NaN. */
+int hotrg_observables(hotrg_ctx *ctx, hotrg_obs *out);
+
+/* Per-site derivatives of ln Z / N at the current step by reverse-mode
+ * differentiation of the whole chain (needs keep_checkpoints = 1):
+ *   *dlnz_dbeta = d(lnZ/N)/d beta  (energy per site e = -dlnz_dbeta),
+ *   *dlnz_dh    = d(lnZ/N)/d h     (magnetisation m = dlnz_dh / beta).
+ * beta must exceed 1e-3 (the chain rule through sqrt(sinh b) diverges at 0). */
+int hotrg_backward(hotrg_ctx *ctx, double *dlnz_dbeta, double *dlnz_dh);
+
+void hotrg_free(hotrg_ctx *ctx);
+const char *hotrg_last_error(void);
+
+/* ---- state access for parity tests and checkpoint/resume ------------------ */
+
+/* Current dims and step count. */
+int hotrg_get_dims(hotrg_ctx *ctx, int dims[4], int *n);
+
+/* Copy tensor `which` (0 = T, 1 = S_m, 2 = S_e) to host memory `out`
+ * (capacity `count` doubles; needs prod_q D_q^2 doubles). */
+int hotrg_get_tensor(hotrg_ctx *ctx, int which, double *out, size_t count);
+
+/* Replace the state by host tensors of dims `dims` (each D_q in 1..max(dcut,2)).
+ * Sm or Se may be NULL when impurities are off.  `n` becomes the step count and
+ * `lnz_acc` the accumulated sum_k 2^-k ln c_k. */
+int hotrg_set_state(hotrg_ctx *ctx, const int dims[4], const double *T, const double *Sm,
+                    const double *Se, int n, double lnz_acc);
+
+/* Step with caller-given isometries instead of the environment/eigh stage:
+ * U[q] (host, row-major D_q^2 x k[q]) for the three transverse axes q != axis
+ * (U[axis] is ignored).  Used to check the contraction on identical inputs. */
+int hotrg_step_with_isometries(hotrg_ctx *ctx, int axis, const double *const U[4], const int k[4]);
+
+/* Host copy of the isometry of axis `q` used in the last step (row-major,
+ * rows*cols doubles) and of the descending spectrum of its (q, side) env. */
+int hotrg_get_isometry(hotrg_ctx *ctx, int q, double *out, size_t count, int *rows, int *cols);
+int hotrg_get_spectrum(hotrg_ctx *ctx, int q, int side, double *out, size_t count, int *len);
+
+/* Accumulated device time (ms, HIP events on the context stream) and launch
+ * count of the contraction GEMM since the last reset, plus the algorithmic
+ * flops those launches covered (2 M N K summed). kernel 0 = contraction GEMM. */
+int hotrg_kernel_stats(hotrg_ctx *ctx, int kernel, double *ms, long long *launches, double *flops);
+int hotrg_reset_stats(hotrg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOTRG_H */

@@ -55,3 +55,11 @@ def _col_vectors(T2, Us, mu, cols):
 def step_entries(T1, T2, Us: dict, mu: int, rows, cols) -> np.ndarray:
     """Matrix of new-tensor entries [len(rows), len(cols)] (unnormalised)."""
     return _row_vectors(T1, Us, mu, rows) @ _col_vectors(T2, Us, mu, cols).T
+
+
+def step_entries_with_norms(T1, T2, Us: dict, mu: int, rows, cols):
+    """Entries plus the Euclidean norms of each row vector and column vector
+    (|entry error| of any summation order is bounded by eps * |row| |col|)."""
+    R1 = _row_vectors(T1, Us, mu, rows)
+    R2 = _col_vectors(T2, Us, mu, cols)
+    return R1 @ R2.T, np.linalg.norm(R1, axis=1), np.linalg.norm(R2, axis=1)

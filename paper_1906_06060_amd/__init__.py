@@ -1,0 +1,7 @@
+"""MI355X-native HOTRG coarse-graining step for the 4D Ising model.
+
+The compute lives in the HIP library libhotrg_gfx950.so (C ABI in
+include/hotrg.h); `paper_1906_06060_amd.hotrg` is its ctypes binding and
+`paper_1906_06060_amd.autograd` wraps ln Z / N as a torch.autograd.Function.
+"""
+from . import hotrg  # noqa: F401

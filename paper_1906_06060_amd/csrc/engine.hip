@@ -1,0 +1,943 @@
+// Host engine and C ABI of the HOTRG library (include/hotrg.h).
+//
+// One context = one coarse-graining state in device memory.  A step along mu
+// (Sec. 2; Eqs. (2.8)-(2.9) in four dimensions) runs entirely on the device:
+//   1. squeezed environments of the merged transverse legs from two Grams each
+//      (HOSVD of the merged tensor), FP64;
+//   2. Jacobi eigendecomposition of every environment, FP64;
+//   3. (host, on the spectra only) truncation and side choice;
+//   4. for every K slice (alpha, a1'): isometry products build the operand
+//      rows A_s (T, S_m, S_e stacked) and columns B_s, then the MFMA GEMM
+//      accumulates C += A_s B_s^T;
+//   5. Frobenius norm c_n of the T block, then C is permuted back to the
+//      canonical leg order and divided by c_n.
+// Index names follow the paper: for a step along mu the transverse axes are
+// a, b, c (increasing axis id); T1 legs (a1, a1', b1, b1', c1, c1', mu1,
+// alpha), T2 legs (a2, a2', b2, b2', c2, c2', alpha, mu2'); new legs a = U
+// over (a1, a2), a' = U over (a1', a2'), etc.
+#include "../../include/hotrg.h"
+#include "hotrg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+using namespace hotrg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+struct Decision {
+    int side = -1;
+    int k = 0;
+    double eps_b = 0, eps_f = 0, gap = INFINITY;
+    bool flagged = false;
+    bool truncated = false;
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+constexpr double kSideTie = 1e-11;
+constexpr int kMaxEnvN = 144;
+
+}  // namespace
+
+struct hotrg_ctx {
+    double beta = 0, h = 0;
+    int dcut = 0;
+    hotrg_config cfg{};
+    hipStream_t stream = nullptr;
+    bool failed = false;
+
+    int dims[4] = {2, 2, 2, 2};
+    int n = 0;
+    int first_axis = -1, last_axis = -1;
+    double lnz_acc = 0;
+    size_t cap = 0;  // elements of the largest tensor, max(2, dcut)^8
+
+    double *state[3] = {nullptr, nullptr, nullptr};  // T, S_m, S_e (canonical layout)
+    double *cbuf = nullptr;                          // 3 * cap: GEMM output rows T | S_m | S_e
+    double *gram_x = nullptr;                        // cap
+    double *y1 = nullptr, *y2 = nullptr;             // cap each
+    double *gram_part = nullptr;
+    size_t gram_part_cap = 0;
+    double *G = nullptr;     // 2 * 144^2 (one pair of Grams at a time)
+    double *E = nullptr;     // 6 * 144^2
+    double *lam = nullptr;   // 6 * 144
+    double *V = nullptr;     // 6 * 144^2
+    double *jwork = nullptr; // 2 * 2 * 145^2
+    int *sweeps = nullptr;
+    double *U[3] = {nullptr, nullptr, nullptr};  // chosen isometries, 144^2 each, row-major n x k
+    double *partials = nullptr;                   // 1024
+    double *scal = nullptr;                       // 64
+    double *obs = nullptr;                        // 3 + 144
+    DevBuf f64_slices;                            // FP64 operand slices
+    DevBuf x3_slices;                             // bf16 hi/lo operand slices
+    std::vector<DevBuf> owned;
+
+    // host-side record of the last step
+    Decision dec[4];
+    std::vector<double> spectra[4][2];
+    int Urows[4] = {0, 0, 0, 0}, Ucols[4] = {0, 0, 0, 0};
+    double min_gap = INFINITY;
+    int flagged = 0;
+    double last_cn = 0;
+
+    // GEMM timing
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double gemm_ms = 0;
+    long long gemm_launches = 0;
+    double gemm_flops = 0;
+    size_t device_bytes = 0;
+};
+
+namespace {
+
+#define HIP_TRY(ctx, call)                                                                          \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            (ctx)->failed = true;                                                                   \
+            return set_err(HOTRG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));       \
+        }                                                                                           \
+    } while (0)
+
+#define TRY(expr)                  \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != HOTRG_OK) return rc_; \
+    } while (0)
+
+int dev_alloc(hotrg_ctx *c, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return set_err(HOTRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                         hipGetErrorString(e));
+    }
+    c->owned.push_back(DevBuf{*p, bytes});
+    c->device_bytes += bytes;
+    return HOTRG_OK;
+}
+
+template <typename T>
+int alloc_n(hotrg_ctx *c, T **p, size_t count) {
+    return dev_alloc(c, (void **)p, count * sizeof(T));
+}
+
+int ensure(hotrg_ctx *c, DevBuf &b, size_t bytes) {
+    if (b.bytes >= bytes) return HOTRG_OK;
+    if (b.p) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (auto &o : c->owned)
+            if (o.p == b.p) {
+                c->device_bytes -= o.bytes;
+                o.p = nullptr;
+                o.bytes = 0;
+            }
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    void *p = nullptr;
+    TRY(dev_alloc(c, &p, bytes));
+    b.p = p;
+    b.bytes = bytes;
+    return HOTRG_OK;
+}
+
+PermParams perm_params(int nd, const int *ext, const uint32_t *in_st, uint64_t *max_in = nullptr) {
+    PermParams p{};
+    p.nd = nd;
+    uint64_t total = 1, mx = 0;
+    for (int k = 0; k < nd; ++k) {
+        p.ext[k] = make_fastdiv((uint32_t)ext[k]);
+        p.in_st[k] = in_st[k];
+        total *= (uint64_t)ext[k];
+        mx += (uint64_t)(ext[k] - 1) * in_st[k];
+    }
+    p.total = (uint32_t)total;
+    if (max_in) *max_in = mx;
+    return p;
+}
+
+// Mode product description helper: output extents with (in stride, U stride)
+// per output dim, one contracted index.
+struct MP {
+    ModeParams p{};
+    uint64_t total = 1;
+    uint64_t max_in = 0, max_u = 0;  // largest element offsets the launch can touch
+    void dim(int ext, uint64_t ist, uint64_t ust) {
+        int k = p.nd++;
+        p.ext[k] = make_fastdiv((uint32_t)ext);
+        p.in_st[k] = (uint32_t)ist;
+        p.u_st[k] = (uint32_t)ust;
+        total *= (uint64_t)ext;
+        max_in += (uint64_t)(ext - 1) * ist;
+        max_u += (uint64_t)(ext - 1) * ust;
+    }
+    void sum(int n, uint64_t ist, uint64_t ust) {
+        p.nsum = n;
+        p.in_sum_st = (uint32_t)ist;
+        p.u_sum_st = (uint32_t)ust;
+        max_in += (uint64_t)(n - 1) * ist;
+        max_u += (uint64_t)(n - 1) * ust;
+    }
+    // host-side bounds check of a launch: input, isometry and output extents
+    // (elements available from each base pointer)
+    bool fits(uint64_t in_avail, uint64_t u_avail, uint64_t out_avail) const {
+        return p.nd <= MP_MAXD && total < (1ull << 31) && max_in < in_avail && max_u < u_avail &&
+               total <= out_avail && max_in < (1ull << 32);
+    }
+    const ModeParams &done() {
+        p.total = (uint32_t)total;
+        return p;
+    }
+};
+
+void row_major_strides(int nd, const int *ext, uint64_t *st) {
+    uint64_t s = 1;
+    for (int k = nd - 1; k >= 0; --k) {
+        st[k] = s;
+        s *= (uint64_t)ext[k];
+    }
+}
+
+size_t tensor_size(const int D[4]) {
+    size_t s = 1;
+    for (int q = 0; q < 4; ++q) s *= (size_t)D[q] * D[q];
+    return s;
+}
+
+// canonical element strides of the 8 legs for dims D
+void canon_strides(const int D[4], uint64_t st[8]) {
+    uint64_t s = 1;
+    for (int l = 7; l >= 0; --l) {
+        st[l] = s;
+        s *= (uint64_t)D[l / 2];
+    }
+}
+
+hipEvent_t next_event(hotrg_ctx *c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+// Reading R3: cut at dcut unless the gap there is <= tau * lam_1; then the
+// largest smaller k with a gap above tau.
+Decision choose_cut(const double *lam, int n, int dcut, double tau) {
+    Decision d;
+    d.truncated = true;
+    double l1 = lam[0];
+    if (!(l1 > 0)) {
+        d.k = dcut;
+        d.gap = 0;
+        d.flagged = true;
+        return d;
+    }
+    auto gap = [&](int k) { return (lam[k - 1] - lam[k]) / l1; };
+    if (gap(dcut) > tau) {
+        d.k = dcut;
+        d.gap = gap(dcut);
+        return d;
+    }
+    for (int k = dcut - 1; k >= 1; --k)
+        if (gap(k) > tau) {
+            d.k = k;
+            d.gap = gap(k);
+            return d;
+        }
+    d.k = dcut;
+    d.gap = gap(dcut);
+    d.flagged = true;
+    return d;
+}
+
+double discarded(const double *lam, int n, int k) {
+    double e = 0;
+    for (int i = k; i < n; ++i) e += std::max(lam[i], 0.0);
+    return e;
+}
+
+// Gram of T with open legs (leg_p, leg_a) in local numbering; local leg l
+// has canonical stride lst[l] and dimension ldim[l].  Result R x R with
+// R = ldim[leg_p] * ldim[leg_a], row index p * Da + a.
+int gram(hotrg_ctx *c, const double *T, const uint64_t lst[8], const int ldim[8], int leg_p, int leg_a, double *G) {
+    int ext[8];
+    uint32_t st[8];
+    int nd = 0;
+    ext[nd] = ldim[leg_p];
+    st[nd++] = (uint32_t)lst[leg_p];
+    ext[nd] = ldim[leg_a];
+    st[nd++] = (uint32_t)lst[leg_a];
+    size_t K = 1;
+    for (int l = 0; l < 8; ++l) {
+        if (l == leg_p || l == leg_a) continue;
+        ext[nd] = ldim[l];
+        st[nd++] = (uint32_t)lst[l];
+        K *= (size_t)ldim[l];
+    }
+    int R = ldim[leg_p] * ldim[leg_a];
+    uint64_t mx = 0;
+    PermParams pp = perm_params(8, ext, st, &mx);
+    if (mx >= c->cap || pp.total > c->cap || R > kMaxEnvN) return set_err(HOTRG_EINVAL, "gram launch out of bounds");
+    launch_permute(pp, T, c->gram_x, 1.0, c->stream);
+    int nchunks = (int)std::min<size_t>(std::max<size_t>(1, K / 512), 1024);
+    size_t need = (size_t)nchunks * R * R;
+    if (need > c->gram_part_cap) return set_err(HOTRG_ENOMEM, "gram partial buffer too small");
+    launch_gram(c->gram_x, R, K, c->gram_part, nchunks, G, c->stream);
+    return HOTRG_OK;
+}
+
+int check_launch(hotrg_ctx *c, const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->failed = true;
+        return set_err(HOTRG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    return HOTRG_OK;
+}
+
+// Environment + eigh + decisions for every transverse axis; fills c->U[i],
+// k[i] (kept), and the decision record.  Local legs: 0..5 transverse
+// (a, a', b, b', c, c'), 6 = mu1 (backward), 7 = mu' (forward).
+int isometries(hotrg_ctx *c, const double *T, const uint64_t lst[8], const int ldim[8], const int tv[3], int mu,
+               int k_out[3]) {
+    const int Dm = ldim[6];
+    for (int q = 0; q < 4; ++q) {
+        c->dec[q] = Decision();
+        c->spectra[q][0].clear();
+        c->spectra[q][1].clear();
+    }
+    c->min_gap = INFINITY;
+    c->flagged = 0;
+    for (int i = 0; i < 3; ++i) {
+        const int D = ldim[2 * i];
+        const int nmat = D * D;
+        int q = tv[i];
+        if (nmat <= c->dcut) {
+            launch_identity(c->U[i], nmat, c->stream);
+            k_out[i] = nmat;
+            c->dec[q].k = nmat;
+            c->Urows[q] = nmat;
+            c->Ucols[q] = nmat;
+            continue;
+        }
+        if (nmat > kMaxEnvN) return set_err(HOTRG_EINVAL, "environment larger than 144 x 144");
+        double *Eb = c->E + (size_t)(2 * i) * kMaxEnvN * kMaxEnvN;
+        for (int side = 0; side < 2; ++side) {
+            int leg = 2 * i + side;
+            double *G1 = c->G, *G2 = c->G + (size_t)kMaxEnvN * kMaxEnvN;
+            TRY(gram(c, T, lst, ldim, leg, 7, G1));
+            TRY(gram(c, T, lst, ldim, leg, 6, G2));
+            launch_env_combine(G1, G2, D, D, Dm, Eb + (size_t)side * nmat * nmat, c->stream);
+        }
+        // both sides share n, so they go in one launch; matrices packed at stride n*n
+        launch_jacobi_eigh(Eb, nmat, 2, c->lam + (size_t)2 * i * kMaxEnvN, c->V + (size_t)2 * i * kMaxEnvN * kMaxEnvN,
+                           c->jwork, c->sweeps, c->stream);
+        TRY(check_launch(c, "environment / eigh"));
+        std::vector<double> lam(2 * (size_t)nmat);
+        HIP_TRY(c, hipMemcpyAsync(lam.data(), c->lam + (size_t)2 * i * kMaxEnvN, sizeof(double) * 2 * nmat,
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        Decision db = choose_cut(lam.data(), nmat, c->dcut, c->cfg.tau_deg);
+        Decision df = choose_cut(lam.data() + nmat, nmat, c->dcut, c->cfg.tau_deg);
+        double eb = discarded(lam.data(), nmat, db.k), ef = discarded(lam.data() + nmat, nmat, df.k);
+        double scale = discarded(lam.data(), nmat, 0);
+        int side = (eb <= ef + kSideTie * scale) ? 0 : 1;
+        Decision d = side == 0 ? db : df;
+        d.side = side;
+        d.eps_b = eb;
+        d.eps_f = ef;
+        c->dec[q] = d;
+        c->spectra[q][0].assign(lam.begin(), lam.begin() + nmat);
+        c->spectra[q][1].assign(lam.begin() + nmat, lam.end());
+        c->min_gap = std::min(c->min_gap, d.gap);
+        c->flagged |= d.flagged ? 1 : 0;
+        // U = first k columns of the chosen side's eigenvectors (row-major n x n) -> n x k
+        const double *Vs = c->V + (size_t)2 * i * kMaxEnvN * kMaxEnvN + (size_t)side * nmat * nmat;
+        HIP_TRY(c, hipMemcpy2DAsync(c->U[i], sizeof(double) * d.k, Vs, sizeof(double) * nmat,
+                                    sizeof(double) * d.k, nmat, hipMemcpyDeviceToDevice, c->stream));
+        k_out[i] = d.k;
+        c->Urows[q] = nmat;
+        c->Ucols[q] = d.k;
+    }
+    (void)mu;
+    return HOTRG_OK;
+}
+
+// Contraction of one step with isometries c->U[0..2] (n_i x k_i, row-major).
+int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
+    const int *D = c->dims;
+    uint64_t cst[8];
+    canon_strides(D, cst);
+    uint64_t lst[8];
+    int ldim[8];
+    for (int i = 0; i < 3; ++i) {
+        lst[2 * i] = cst[2 * tv[i]];
+        lst[2 * i + 1] = cst[2 * tv[i] + 1];
+        ldim[2 * i] = ldim[2 * i + 1] = D[tv[i]];
+    }
+    lst[6] = cst[2 * mu];
+    lst[7] = cst[2 * mu + 1];
+    ldim[6] = ldim[7] = D[mu];
+    const int Da = D[tv[0]], Db = D[tv[1]], Dc = D[tv[2]], Dm = D[mu];
+    const int ka = k[0], kb = k[1], kc = k[2];
+    const uint64_t M = (uint64_t)ka * kb * kc * Dm;  // rows of one tensor = columns
+    const uint64_t Ks = (uint64_t)Db * Dc * Da * Db * Dc;
+    const bool imp = c->cfg.impurities != 0;
+    const bool se_pair = imp && c->n == 0;  // Eq. (2.8): S_e . S_e on the first step
+    const int nA = imp ? 3 : 1;
+    const int nA_shared = se_pair ? 2 : nA;  // operands multiplying B(T)
+    if (M * Ks >= (1ull << 31)) return set_err(HOTRG_ENOMEM, "operand slice exceeds 2^31 elements");
+    if (M * M * 3 > c->cap * 3) return set_err(HOTRG_EINVAL, "new tensor exceeds capacity");
+    const bool mixed = c->cfg.precision == HOTRG_BF16X3 && (c->n + 1) >= c->cfg.mixed_from_step &&
+                       (Ks % 16 == 0);
+    const uint64_t slice = M * Ks;
+    const int nB = se_pair ? 2 : 1;
+    double *Asl = nullptr, *Bsl = nullptr;
+    uint16_t *Ah = nullptr, *Al = nullptr, *Bh = nullptr, *Bl = nullptr;
+    if (mixed) {
+        TRY(ensure(c, c->x3_slices, sizeof(uint16_t) * 2 * slice * (nA + nB)));
+        Ah = (uint16_t *)c->x3_slices.p;
+        Al = Ah + slice * nA;
+        Bh = Al + slice * nA;
+        Bl = Bh + slice * nB;
+    } else {
+        TRY(ensure(c, c->f64_slices, sizeof(double) * slice * (nA + nB)));
+        Asl = (double *)c->f64_slices.p;
+        Bsl = Asl + slice * nA;
+    }
+    double *Ua = c->U[0], *Ub = c->U[1], *Uc = c->U[2];
+    const uint64_t usz[3] = {(uint64_t)Da * Da * ka, (uint64_t)Db * Db * kb, (uint64_t)Dc * Dc * kc};
+    const uint64_t tsize = tensor_size(D);
+    c->ev_used = 0;
+
+    // intermediate strides
+    const int y1e[7] = {ka, Da, Db, Db, Dc, Dc, Dm};
+    uint64_t y1s[7];
+    row_major_strides(7, y1e, y1s);
+    const int y2e[8] = {ka, Da, kb, Db, Db, Dc, Dc, Dm};
+    uint64_t y2s[8];
+    row_major_strides(8, y2e, y2s);
+    // Q-side intermediates use the same extents pattern
+    const int z1e[7] = {ka, Da, Db, Db, Dc, Dc, Dm};
+    uint64_t z1s[7];
+    row_major_strides(7, z1e, z1s);
+    const int z2e[8] = {ka, Da, kb, Db, Db, Dc, Dc, Dm};
+    uint64_t z2s[8];
+    row_major_strides(8, z2e, z2s);
+
+    bool first_slice = true;
+    for (int g = 0; g < Dm; ++g) {       // alpha
+        for (int f = 0; f < Da; ++f) {   // a1'
+            // ---- A rows: T1 in {T, S_m, S_e}
+            for (int t = 0; t < nA; ++t) {
+                const double *X1 = c->state[t] + f * lst[1] + g * lst[7];
+                {   // P1: Y1[a,a2,b1,b1',c1,c1',mu1] = sum_a1 Ua[(a1,a2),a] X1[a1,f,b1,b1',c1,c1',mu1,g]
+                    MP m;
+                    m.dim(ka, 0, 1);
+                    m.dim(Da, 0, ka);
+                    m.dim(Db, lst[2], 0);
+                    m.dim(Db, lst[3], 0);
+                    m.dim(Dc, lst[4], 0);
+                    m.dim(Dc, lst[5], 0);
+                    m.dim(Dm, lst[6], 0);
+                    m.sum(Da, lst[0], (uint64_t)Da * ka);
+                    if (!m.fits(tsize - (f * lst[1] + g * lst[7]), usz[0], c->cap))
+                        return set_err(HOTRG_EINVAL, "P1 launch out of bounds");
+                    launch_mode_product(m.done(), X1, Ua, c->y1, c->stream);
+                }
+                {   // P2: Y2[a,a2,b,b2,b1',c1,c1',mu1] = sum_b1 Ub[(b1,b2),b] Y1[a,a2,b1,b1',c1,c1',mu1]
+                    MP m;
+                    m.dim(ka, y1s[0], 0);
+                    m.dim(Da, y1s[1], 0);
+                    m.dim(kb, 0, 1);
+                    m.dim(Db, 0, kb);
+                    m.dim(Db, y1s[3], 0);
+                    m.dim(Dc, y1s[4], 0);
+                    m.dim(Dc, y1s[5], 0);
+                    m.dim(Dm, y1s[6], 0);
+                    m.sum(Db, y1s[2], (uint64_t)Db * kb);
+                    if (!m.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "P2 launch out of bounds");
+                    launch_mode_product(m.done(), c->y1, Ub, c->y2, c->stream);
+                }
+                {   // P3: A[(a,b,c,mu1),(b1',c1',a2,b2,c2)] = sum_c1 Uc[(c1,c2),c] Y2[a,a2,b,b2,b1',c1,c1',mu1]
+                    MP m;
+                    m.dim(ka, y2s[0], 0);
+                    m.dim(kb, y2s[2], 0);
+                    m.dim(kc, 0, 1);
+                    m.dim(Dm, y2s[7], 0);
+                    m.dim(Db, y2s[4], 0);
+                    m.dim(Dc, y2s[6], 0);
+                    m.dim(Da, y2s[1], 0);
+                    m.dim(Db, y2s[3], 0);
+                    m.dim(Dc, 0, kc);
+                    m.sum(Dc, y2s[5], (uint64_t)Dc * kc);
+                    if (!m.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
+                    if (mixed)
+                        launch_mode_product_split(m.done(), c->y2, Uc, Ah + slice * t, Al + slice * t, c->stream);
+                    else
+                        launch_mode_product(m.done(), c->y2, Uc, Asl + slice * t, c->stream);
+                }
+            }
+            // ---- B columns: T2 = T (and S_e for the first-step pair)
+            for (int bidx = 0; bidx < nB; ++bidx) {
+                const double *X2 = c->state[bidx == 0 ? 0 : 2] + g * lst[6];
+                {   // Q1: Z1[a',a2,b2,b2',c2,c2',mu2'] = sum_a2' Ua[(f,a2'),a'] X2[a2,a2',b2,b2',c2,c2',g,mu2']
+                    MP m;
+                    m.dim(ka, 0, 1);
+                    m.dim(Da, lst[0], 0);
+                    m.dim(Db, lst[2], 0);
+                    m.dim(Db, lst[3], 0);
+                    m.dim(Dc, lst[4], 0);
+                    m.dim(Dc, lst[5], 0);
+                    m.dim(Dm, lst[7], 0);
+                    m.sum(Da, lst[1], ka);
+                    if (!m.fits(tsize - g * lst[6], usz[0] - (uint64_t)f * Da * ka, c->cap))
+                        return set_err(HOTRG_EINVAL, "Q1 launch out of bounds");
+                    launch_mode_product(m.done(), X2, Ua + (size_t)f * Da * ka, c->y1, c->stream);
+                }
+                {   // Q2: Z2[a',a2,b',b1',b2,c2,c2',mu2'] = sum_b2' Ub[(b1',b2'),b'] Z1[a',a2,b2,b2',c2,c2',mu2']
+                    MP m;
+                    m.dim(ka, z1s[0], 0);
+                    m.dim(Da, z1s[1], 0);
+                    m.dim(kb, 0, 1);
+                    m.dim(Db, 0, (uint64_t)Db * kb);
+                    m.dim(Db, z1s[2], 0);
+                    m.dim(Dc, z1s[4], 0);
+                    m.dim(Dc, z1s[5], 0);
+                    m.dim(Dm, z1s[6], 0);
+                    m.sum(Db, z1s[3], kb);
+                    if (!m.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "Q2 launch out of bounds");
+                    launch_mode_product(m.done(), c->y1, Ub, c->y2, c->stream);
+                }
+                {   // Q3: Bt[(a',b',c',mu2'),(b1',c1',a2,b2,c2)] = sum_c2' Uc[(c1',c2'),c'] Z2[a',a2,b',b1',b2,c2,c2',mu2']
+                    MP m;
+                    m.dim(ka, z2s[0], 0);
+                    m.dim(kb, z2s[2], 0);
+                    m.dim(kc, 0, 1);
+                    m.dim(Dm, z2s[7], 0);
+                    m.dim(Db, z2s[3], 0);
+                    m.dim(Dc, 0, (uint64_t)Dc * kc);
+                    m.dim(Da, z2s[1], 0);
+                    m.dim(Db, z2s[4], 0);
+                    m.dim(Dc, z2s[5], 0);
+                    m.sum(Dc, z2s[6], kc);
+                    if (!m.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
+                    if (mixed)
+                        launch_mode_product_split(m.done(), c->y2, Uc, Bh + slice * bidx, Bl + slice * bidx,
+                                                  c->stream);
+                    else
+                        launch_mode_product(m.done(), c->y2, Uc, Bsl + slice * bidx, c->stream);
+                }
+            }
+            // ---- GEMMs: C rows (+)= A B^T
+            for (int bidx = 0; bidx < nB; ++bidx) {
+                const int row0 = bidx == 0 ? 0 : 2;
+                const int rows = bidx == 0 ? nA_shared : 1;
+                hipEvent_t e0 = next_event(c), e1 = next_event(c);
+                if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
+                double *Cp = c->cbuf + (size_t)row0 * M * M;
+                if (mixed)
+                    launch_gemm_bf16x3(Ah + slice * row0, Al + slice * row0, Bh + slice * bidx, Bl + slice * bidx, Cp,
+                                       (int)(M * rows), (int)M, (int)Ks, Ks, Ks, M, first_slice ? 0 : 1, c->stream);
+                else
+                    launch_gemm_f64(Asl + slice * row0, Bsl + slice * bidx, Cp, (int)(M * rows), (int)M, (int)Ks, Ks,
+                                    Ks, M, first_slice ? 0 : 1, c->stream);
+                if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+                c->gemm_launches++;
+                c->gemm_flops += 2.0 * (double)(M * rows) * (double)M * (double)Ks;
+            }
+            first_slice = false;
+            TRY(check_launch(c, "contraction slice"));
+        }
+    }
+    return HOTRG_OK;
+}
+
+// c_n = |C_T|_F; state <- perm(C)/c_n; ln Z bookkeeping.
+int finish_step(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
+    int Dn[4];
+    for (int q = 0; q < 4; ++q) Dn[q] = c->dims[q];
+    for (int i = 0; i < 3; ++i) Dn[tv[i]] = k[i];
+    const int Dm = c->dims[mu];
+    const uint64_t M = (uint64_t)k[0] * k[1] * k[2] * Dm;
+    launch_sumsq(c->cbuf, (size_t)(M * M), c->partials, 1024, c->scal, c->stream);
+    double ss = 0;
+    HIP_TRY(c, hipMemcpyAsync(&ss, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // accumulate GEMM event times of this step
+    for (size_t e = 0; e + 1 < c->ev_used; e += 2) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, c->ev_pool[e], c->ev_pool[e + 1]) == hipSuccess) c->gemm_ms += ms;
+    }
+    c->ev_used = 0;
+    double cn = std::sqrt(ss);
+    if (!(cn > 0) || !std::isfinite(cn)) {
+        c->failed = true;
+        return set_err(HOTRG_ENUMERIC, "norm of the new tensor is not finite and positive at step " +
+                                           std::to_string(c->n + 1));
+    }
+    // C row index ((a kb + b) kc + c) Dm + mu1, column likewise with primes
+    const uint64_t cs_a = (uint64_t)k[1] * k[2] * Dm, cs_b = (uint64_t)k[2] * Dm, cs_c = Dm;
+    const uint64_t rowst = M;
+    int ext[8];
+    uint32_t st[8];
+    for (int q = 0; q < 4; ++q) {
+        ext[2 * q] = ext[2 * q + 1] = Dn[q];
+        if (q == mu) {
+            st[2 * q] = (uint32_t)rowst;
+            st[2 * q + 1] = 1;
+        } else {
+            int i = (q == tv[0]) ? 0 : (q == tv[1] ? 1 : 2);
+            uint64_t s = i == 0 ? cs_a : (i == 1 ? cs_b : cs_c);
+            st[2 * q] = (uint32_t)(s * rowst);
+            st[2 * q + 1] = (uint32_t)s;
+        }
+    }
+    uint64_t mx = 0;
+    PermParams pp = perm_params(8, ext, st, &mx);
+    if (mx >= M * M || pp.total != M * M || M * M > c->cap)
+        return set_err(HOTRG_EINVAL, "normalise / permute launch out of bounds");
+    const int nt = c->cfg.impurities ? 3 : 1;
+    for (int t = 0; t < nt; ++t)
+        launch_permute(pp, c->cbuf + (size_t)t * M * M, c->state[t], 1.0 / cn, c->stream);
+    TRY(check_launch(c, "normalise / permute"));
+    c->n += 1;
+    c->last_cn = cn;
+    c->lnz_acc += std::ldexp(std::log(cn), -c->n);
+    for (int q = 0; q < 4; ++q) c->dims[q] = Dn[q];
+    if (c->first_axis < 0) c->first_axis = mu;
+    c->last_axis = mu;
+    return HOTRG_OK;
+}
+
+void transverse_of(int mu, int tv[3]) {
+    int j = 0;
+    for (int q = 0; q < 4; ++q)
+        if (q != mu) tv[j++] = q;
+}
+
+int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost) {
+    if (!c) return set_err(HOTRG_EINVAL, "null context");
+    if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
+    if (axis < 0 || axis > 3) return set_err(HOTRG_EINVAL, "axis must be 0..3");
+    int tv[3];
+    transverse_of(axis, tv);
+    uint64_t cst[8];
+    canon_strides(c->dims, cst);
+    uint64_t lst[8];
+    int ldim[8];
+    for (int i = 0; i < 3; ++i) {
+        lst[2 * i] = cst[2 * tv[i]];
+        lst[2 * i + 1] = cst[2 * tv[i] + 1];
+        ldim[2 * i] = ldim[2 * i + 1] = c->dims[tv[i]];
+    }
+    lst[6] = cst[2 * axis];
+    lst[7] = cst[2 * axis + 1];
+    ldim[6] = ldim[7] = c->dims[axis];
+    int k[3];
+    if (Uhost) {
+        for (int q = 0; q < 4; ++q) c->dec[q] = Decision();
+        for (int i = 0; i < 3; ++i) {
+            int q = tv[i];
+            int nmat = c->dims[q] * c->dims[q];
+            if (!Uhost[q] || khost[q] < 1 || khost[q] > std::max(c->dcut, 2) || khost[q] > nmat)
+                return set_err(HOTRG_EINVAL, "isometry for a transverse axis missing or k out of range");
+            HIP_TRY(c, hipMemcpyAsync(c->U[i], Uhost[q], sizeof(double) * nmat * khost[q], hipMemcpyHostToDevice,
+                                      c->stream));
+            k[i] = khost[q];
+            c->dec[q].k = k[i];
+            c->Urows[q] = nmat;
+            c->Ucols[q] = k[i];
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    } else {
+        TRY(isometries(c, c->state[0], lst, ldim, tv, axis, k));
+    }
+    TRY(contract(c, axis, tv, k));
+    return finish_step(c, axis, tv, k);
+}
+
+int read_obs(hotrg_ctx *c, double *tr, double *trm, double *tre, std::vector<double> *A) {
+    int axis = c->last_axis < 0 ? 3 : c->last_axis;
+    const double *s1 = c->cfg.impurities ? c->state[1] : nullptr;
+    const double *s2 = c->cfg.impurities ? c->state[2] : nullptr;
+    launch_trace_obs(c->state[0], s1, s2, c->dims, axis, c->obs, c->stream);
+    TRY(check_launch(c, "trace"));
+    int Da = c->dims[axis];
+    std::vector<double> h(3 + (size_t)Da * Da);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), c->obs, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *tr = h[0];
+    *trm = h[1];
+    *tre = h[2];
+    if (A) A->assign(h.begin() + 3, h.end());
+    return HOTRG_OK;
+}
+
+}  // namespace
+
+// =============================================================== C ABI ====
+extern "C" {
+
+const char *hotrg_last_error(void) { return g_err.c_str(); }
+
+int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotrg_ctx **out) {
+    if (!out) return set_err(HOTRG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!(beta >= 0) || !std::isfinite(beta)) return set_err(HOTRG_EINVAL, "beta must be finite and >= 0");
+    if (!std::isfinite(h)) return set_err(HOTRG_EINVAL, "h must be finite");
+    if (dcut < 1 || dcut > 12) return set_err(HOTRG_EINVAL, "dcut must be in 1..12");
+    hotrg_ctx *c = new hotrg_ctx();
+    c->beta = beta;
+    c->h = h;
+    c->dcut = dcut;
+    if (cfg) c->cfg = *cfg;
+    else {
+        c->cfg.impurities = 1;
+    }
+    if (c->cfg.precision != HOTRG_FP64 && c->cfg.precision != HOTRG_BF16X3) {
+        delete c;
+        return set_err(HOTRG_EINVAL, "unknown precision");
+    }
+    if (c->cfg.mixed_from_step <= 0) c->cfg.mixed_from_step = 4;
+    if (!(c->cfg.tau_deg > 0)) c->cfg.tau_deg = 1e-12;
+    c->stream = (hipStream_t)c->cfg.stream;
+    const int Dmax = std::max(dcut, 2);
+    size_t cap = 1;
+    for (int i = 0; i < 8; ++i) cap *= (size_t)Dmax;
+    c->cap = cap;
+    const size_t E2 = (size_t)kMaxEnvN * kMaxEnvN;
+    int rc = HOTRG_OK;
+    auto fail = [&](int r) {
+        hotrg_free(c);
+        return r;
+    };
+    for (int t = 0; t < 3; ++t)
+        if ((rc = alloc_n(c, &c->state[t], cap))) return fail(rc);
+    if ((rc = alloc_n(c, &c->cbuf, 3 * cap))) return fail(rc);
+    if ((rc = alloc_n(c, &c->gram_x, cap))) return fail(rc);
+    if ((rc = alloc_n(c, &c->y1, cap))) return fail(rc);
+    if ((rc = alloc_n(c, &c->y2, cap))) return fail(rc);
+    c->gram_part_cap = (size_t)1024 * E2;
+    if ((rc = alloc_n(c, &c->gram_part, c->gram_part_cap))) return fail(rc);
+    if ((rc = alloc_n(c, &c->G, 2 * E2))) return fail(rc);
+    if ((rc = alloc_n(c, &c->E, 6 * E2))) return fail(rc);
+    if ((rc = alloc_n(c, &c->lam, 6 * (size_t)kMaxEnvN))) return fail(rc);
+    if ((rc = alloc_n(c, &c->V, 6 * E2))) return fail(rc);
+    if ((rc = alloc_n(c, &c->jwork, (size_t)4 * (kMaxEnvN + 1) * (kMaxEnvN + 1)))) return fail(rc);
+    if ((rc = alloc_n(c, &c->sweeps, 8))) return fail(rc);
+    for (int i = 0; i < 3; ++i)
+        if ((rc = alloc_n(c, &c->U[i], E2))) return fail(rc);
+    if ((rc = alloc_n(c, &c->partials, 1024))) return fail(rc);
+    if ((rc = alloc_n(c, &c->scal, 64))) return fail(rc);
+    if ((rc = alloc_n(c, &c->obs, 3 + (size_t)kMaxEnvN))) return fail(rc);
+
+    // T^(0), S^(0) (Eqs. (2.2), (2.6)); W from the bond matrix (Eq. (2.1))
+    const double wc = std::sqrt(std::cosh(beta)), ws = std::sqrt(std::sinh(beta));
+    launch_init_site(c->state[0], c->state[1], wc, ws, wc, -ws, std::exp(beta * h), std::exp(-beta * h), c->stream);
+    launch_sumsq(c->state[0], 256, c->partials, 1, c->scal, c->stream);
+    double ss = 0;
+    if (hipMemcpyAsync(&ss, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(set_err(HOTRG_EDEVICE, "initial tensor upload failed"));
+    double c0 = std::sqrt(ss);
+    if (!(c0 > 0) || !std::isfinite(c0)) return fail(set_err(HOTRG_ENUMERIC, "initial norm not finite"));
+    int ext[1] = {256};
+    uint32_t st[1] = {1};
+    PermParams pp = perm_params(1, ext, st);
+    launch_permute(pp, c->state[0], c->cbuf, 1.0 / c0, c->stream);
+    launch_permute(pp, c->state[1], c->cbuf + 256, 1.0 / c0, c->stream);
+    launch_permute(pp, c->cbuf, c->state[0], 1.0, c->stream);
+    launch_permute(pp, c->cbuf + 256, c->state[1], 1.0, c->stream);
+    launch_permute(pp, c->cbuf + 256, c->state[2], 1.0, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(set_err(HOTRG_EDEVICE, "init kernels failed"));
+    c->lnz_acc = std::log(c0);
+    *out = c;
+    return HOTRG_OK;
+}
+
+int hotrg_init(double beta, double h, int dcut, hotrg_ctx **out) { return hotrg_init_ex(beta, h, dcut, nullptr, out); }
+
+int hotrg_step(hotrg_ctx *ctx, int axis) { return do_step(ctx, axis, nullptr, nullptr); }
+
+int hotrg_step_with_isometries(hotrg_ctx *ctx, int axis, const double *const U[4], const int k[4]) {
+    if (!U || !k) return set_err(HOTRG_EINVAL, "U or k is NULL");
+    return do_step(ctx, axis, U, k);
+}
+
+int hotrg_lnZ(hotrg_ctx *c, double *lnz) {
+    if (!c || !lnz) return set_err(HOTRG_EINVAL, "null argument");
+    if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
+    double tr, trm, tre;
+    TRY(read_obs(c, &tr, &trm, &tre, nullptr));
+    if (!(tr > 0) || !std::isfinite(tr)) {
+        c->failed = true;
+        return set_err(HOTRG_ENUMERIC, "Tr T is not finite and positive");
+    }
+    *lnz = c->lnz_acc + std::ldexp(std::log(tr), -c->n);
+    return HOTRG_OK;
+}
+
+int hotrg_observables(hotrg_ctx *c, hotrg_obs *o) {
+    if (!c || !o) return set_err(HOTRG_EINVAL, "null argument");
+    if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
+    double tr, trm, tre;
+    std::vector<double> A;
+    TRY(read_obs(c, &tr, &trm, &tre, &A));
+    std::memset(o, 0, sizeof(*o));
+    o->n = c->n;
+    for (int q = 0; q < 4; ++q) o->dims[q] = c->dims[q];
+    // a state set by the caller may have Tr <= 0; ln Z is then undefined (NaN)
+    o->lnz_per_site = (tr > 0 && std::isfinite(tr)) ? c->lnz_acc + std::ldexp(std::log(tr), -c->n) : NAN;
+    o->trace = tr;
+    if (c->cfg.impurities) {
+        o->m_imp = trm / tr;
+        o->nn_imp = tre / tr;
+        o->e_imp = -4.0 * o->nn_imp - c->h * o->m_imp;
+    } else {
+        o->m_imp = o->nn_imp = o->e_imp = NAN;
+    }
+    int Da = c->dims[c->last_axis < 0 ? 3 : c->last_axis];
+    double trA = 0, trA2 = 0;
+    for (int t = 0; t < Da; ++t) {
+        trA += A[(size_t)t * Da + t];
+        for (int u = 0; u < Da; ++u) trA2 += A[(size_t)t * Da + u] * A[(size_t)u * Da + t];
+    }
+    o->X = trA * trA / trA2;
+    o->last_axis = c->last_axis;
+    o->min_cut_gap = c->min_gap;
+    o->flagged = c->flagged;
+    for (int q = 0; q < 4; ++q) {
+        o->last_side[q] = c->dec[q].truncated ? c->dec[q].side : -1;
+        o->last_k[q] = c->dec[q].k;
+        o->last_eps[q] = c->dec[q].side == 1 ? c->dec[q].eps_f : c->dec[q].eps_b;
+    }
+    o->last_cn = c->last_cn;
+    o->device_bytes = c->device_bytes;
+    return HOTRG_OK;
+}
+
+int hotrg_backward(hotrg_ctx *c, double *dbeta, double *dh) {
+    if (!c || !dbeta || !dh) return set_err(HOTRG_EINVAL, "null argument");
+    return set_err(HOTRG_ESTATE, "backward pass not available in this build");
+}
+
+void hotrg_free(hotrg_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto &o : c->owned)
+        if (o.p) (void)hipFree(o.p);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int hotrg_get_dims(hotrg_ctx *c, int dims[4], int *n) {
+    if (!c || !dims) return set_err(HOTRG_EINVAL, "null argument");
+    for (int q = 0; q < 4; ++q) dims[q] = c->dims[q];
+    if (n) *n = c->n;
+    return HOTRG_OK;
+}
+
+int hotrg_get_tensor(hotrg_ctx *c, int which, double *out, size_t count) {
+    if (!c || !out) return set_err(HOTRG_EINVAL, "null argument");
+    if (which < 0 || which > 2) return set_err(HOTRG_EINVAL, "which must be 0, 1 or 2");
+    if (which > 0 && !c->cfg.impurities) return set_err(HOTRG_ESTATE, "impurities are off");
+    size_t need = tensor_size(c->dims);
+    if (count < need) return set_err(HOTRG_EINVAL, "output buffer too small");
+    HIP_TRY(c, hipMemcpyAsync(out, c->state[which], sizeof(double) * need, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return HOTRG_OK;
+}
+
+int hotrg_set_state(hotrg_ctx *c, const int dims[4], const double *T, const double *Sm, const double *Se, int n,
+                    double lnz_acc) {
+    if (!c || !dims || !T) return set_err(HOTRG_EINVAL, "null argument");
+    if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
+    const int Dmax = std::max(c->dcut, 2);
+    for (int q = 0; q < 4; ++q)
+        if (dims[q] < 1 || dims[q] > Dmax) return set_err(HOTRG_EINVAL, "dims out of range");
+    if (c->cfg.impurities && (!Sm || !Se)) return set_err(HOTRG_EINVAL, "impure tensors required");
+    if (n < 0) return set_err(HOTRG_EINVAL, "n must be >= 0");
+    size_t need = tensor_size(dims);
+    HIP_TRY(c, hipMemcpyAsync(c->state[0], T, sizeof(double) * need, hipMemcpyHostToDevice, c->stream));
+    if (c->cfg.impurities) {
+        HIP_TRY(c, hipMemcpyAsync(c->state[1], Sm, sizeof(double) * need, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->state[2], Se, sizeof(double) * need, hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int q = 0; q < 4; ++q) c->dims[q] = dims[q];
+    c->n = n;
+    c->lnz_acc = lnz_acc;
+    c->first_axis = n > 0 ? 0 : -1;
+    c->last_axis = -1;
+    return HOTRG_OK;
+}
+
+int hotrg_get_isometry(hotrg_ctx *c, int q, double *out, size_t count, int *rows, int *cols) {
+    if (!c || !out || q < 0 || q > 3) return set_err(HOTRG_EINVAL, "bad argument");
+    if (c->last_axis < 0 || q == c->last_axis) return set_err(HOTRG_ESTATE, "no isometry for this axis");
+    int tv[3];
+    transverse_of(c->last_axis, tv);
+    int i = (q == tv[0]) ? 0 : (q == tv[1] ? 1 : 2);
+    size_t need = (size_t)c->Urows[q] * c->Ucols[q];
+    if (count < need) return set_err(HOTRG_EINVAL, "output buffer too small");
+    HIP_TRY(c, hipMemcpyAsync(out, c->U[i], sizeof(double) * need, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (rows) *rows = c->Urows[q];
+    if (cols) *cols = c->Ucols[q];
+    return HOTRG_OK;
+}
+
+int hotrg_get_spectrum(hotrg_ctx *c, int q, int side, double *out, size_t count, int *len) {
+    if (!c || q < 0 || q > 3 || side < 0 || side > 1) return set_err(HOTRG_EINVAL, "bad argument");
+    const auto &s = c->spectra[q][side];
+    if (len) *len = (int)s.size();
+    if (out) {
+        if (count < s.size()) return set_err(HOTRG_EINVAL, "output buffer too small");
+        std::copy(s.begin(), s.end(), out);
+    }
+    return HOTRG_OK;
+}
+
+int hotrg_kernel_stats(hotrg_ctx *c, int kernel, double *ms, long long *launches, double *flops) {
+    if (!c || kernel != 0) return set_err(HOTRG_EINVAL, "bad argument");
+    if (ms) *ms = c->gemm_ms;
+    if (launches) *launches = c->gemm_launches;
+    if (flops) *flops = c->gemm_flops;
+    return HOTRG_OK;
+}
+
+int hotrg_reset_stats(hotrg_ctx *c) {
+    if (!c) return set_err(HOTRG_EINVAL, "null context");
+    c->gemm_ms = 0;
+    c->gemm_launches = 0;
+    c->gemm_flops = 0;
+    return HOTRG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,276 @@
+// Contraction GEMMs of the HOTRG step on the gfx950 matrix cores.
+//
+//   C[M x N] (+)= A[M x K] * B[N x K]^T,   both operands K-contiguous.
+//
+// The O(D^15) contraction of Sec. 2 (cost paragraph) is exactly this
+// product with M = N = D^4 and K = D^7 (taken in K slices), so both kernels
+// are plain LDS-staged MFMA tile loops:
+//   * gemm_f64:    v_mfma_f64_16x16x4_f64, 128 x 128 tile, 4 waves of 64 x 64;
+//   * gemm_bf16x3: v_mfma_f32_32x32x16_bf16 on hi/lo splits (3 products),
+//                  256 x 256 tile, 4 waves of 128 x 128, FP32 accumulation
+//                  inside chunks of 8192 k; each chunk is added into the FP64
+//                  output tile (owned by one workgroup, so no atomics).
+// Tiles are ordered so that the blocks an XCD runs together form a compact
+// patch of the output (shared A rows / B columns stay in that XCD's L2).
+#include "hotrg_internal.h"
+
+namespace hotrg {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// blockIdx.x -> (tile row, tile col): round-robin XCD dispatch undone, then
+// groups of `G` tile rows walked column by column.
+__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn) {
+    const int nb = tiles_m * tiles_n;
+    const int full = nb - nb % 8;
+    int t = bid < full ? (bid % 8) * (full / 8) + bid / 8 : bid;
+    const int G = 8;
+    const int per_group = G * tiles_n;
+    const int group = t / per_group;
+    const int first = group * G;
+    const int gsize = min(tiles_m - first, G);
+    const int r = t % per_group;
+    tm = first + r % gsize;
+    tn = r / gsize;
+}
+
+// ------------------------------------------------------------------ FP64 ---
+namespace f64 {
+constexpr int BM = 128, BN = 128, BK = 16, PAD = 4, NT = 256;
+
+__global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__ A, const double *__restrict__ B,
+                                                      double *__restrict__ C, int M, int N, int K, size_t lda,
+                                                      size_t ldb, size_t ldc, int accumulate, int tiles_m,
+                                                      int tiles_n) {
+    __shared__ double As[BK][BM + PAD];
+    __shared__ double Bs[BK][BN + PAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int lr = tid >> 1, kp = (tid & 1) * 8;
+    const bool arow = (m0 + lr) < M, brow = (n0 + lr) < N;
+    const double *Ap = A + (size_t)(arow ? m0 + lr : 0) * lda;
+    const double *Bp = B + (size_t)(brow ? n0 + lr : 0) * ldb;
+
+    dbl4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    double ra[8], rb[8];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int k = k0 + kp + j;
+            ra[j] = (arow && k < K) ? Ap[k] : 0.0;
+            rb[j] = (brow && k < K) ? Bp[k] : 0.0;
+        }
+    };
+    gload(0);
+    const int i16 = lane & 15, k4 = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            As[kp + j][lr] = ra[j];
+            Bs[kp + j][lr] = rb[j];
+        }
+        __syncthreads();
+        if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+        for (int kq = 0; kq < BK / 4; ++kq) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kq * 4 + k4][wr * 64 + i * 16 + i16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kq * 4 + k4][wc * 64 + j * 16 + i16];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D layout of the 16x16 f64 block: value r of lane l is row l/16 + 4 r, column l%16
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = m0 + wr * 64 + i * 16 + k4 + 4 * r;
+                int col = n0 + wc * 64 + j * 16 + i16;
+                if (row < M && col < N) {
+                    double *c = C + (size_t)row * ldc + col;
+                    *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+                }
+            }
+}
+}  // namespace f64
+
+void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, int K, size_t lda, size_t ldb,
+                     size_t ldc, int accumulate, hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    int tm = (M + f64::BM - 1) / f64::BM, tn = (N + f64::BN - 1) / f64::BN;
+    f64::gemm_f64_kernel<<<tm * tn, f64::NT, 0, s>>>(A, B, C, M, N, K, lda, ldb, ldc, accumulate, tm, tn);
+}
+
+// ---------------------------------------------------------------- bf16x3 ---
+namespace x3 {
+constexpr int BM = 256, BN = 256, BK = 16, PAD = 8, NT = 256;
+constexpr int KC = 8192;  // k per FP32 accumulation chunk
+constexpr int LDK = BK + PAD;
+constexpr size_t LDS_OPERANDS = (size_t)(2 * BM + 2 * BN) * LDK * sizeof(uint16_t);
+constexpr size_t LDS_FLUSH = (size_t)4 * 32 * 129 * sizeof(float);
+constexpr size_t LDS_BYTES = LDS_OPERANDS > LDS_FLUSH ? LDS_OPERANDS : LDS_FLUSH;
+
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restrict__ Ah,
+                                                         const uint16_t *__restrict__ Al,
+                                                         const uint16_t *__restrict__ Bh,
+                                                         const uint16_t *__restrict__ Bl, double *__restrict__ C,
+                                                         int M, int N, int K, size_t lda, size_t ldb, size_t ldc,
+                                                         int accumulate, int tiles_m, int tiles_n) {
+    extern __shared__ __align__(16) uint16_t smem[];
+    uint16_t *sAh = smem;
+    uint16_t *sAl = sAh + BM * LDK;
+    uint16_t *sBh = sAl + BM * LDK;
+    uint16_t *sBl = sBh + BN * LDK;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;  // wave tile: rows wr*128.., cols wc*128..
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    // global -> register mapping: thread t owns row t of every operand tile (64 bytes)
+    const int lr = tid;
+    const bool arow = (m0 + lr) < M, brow = (n0 + lr) < N;
+    const uint16_t *pAh = Ah + (size_t)(arow ? m0 + lr : 0) * lda;
+    const uint16_t *pAl = Al + (size_t)(arow ? m0 + lr : 0) * lda;
+    const uint16_t *pBh = Bh + (size_t)(brow ? n0 + lr : 0) * ldb;
+    const uint16_t *pBl = Bl + (size_t)(brow ? n0 + lr : 0) * ldb;
+
+    constexpr int NQ = BK / 8;  // 16-byte pieces per row and operand
+    u4 r[4 * NQ];
+    const u4 zero = {0u, 0u, 0u, 0u};
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            r[q] = arow ? *(const u4 *)(pAh + k0 + 8 * q) : zero;
+            r[NQ + q] = arow ? *(const u4 *)(pAl + k0 + 8 * q) : zero;
+            r[2 * NQ + q] = brow ? *(const u4 *)(pBh + k0 + 8 * q) : zero;
+            r[3 * NQ + q] = brow ? *(const u4 *)(pBl + k0 + 8 * q) : zero;
+        }
+    };
+
+    flt16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    // D layout of the 32x32 block: lane l, value e -> row 8*(e/4) + 4*(l/32) + e%4, column l%32
+    const int i32 = lane & 31, kh = (lane >> 5) * 8, lq = (lane >> 5) * 4;
+    bool first = !accumulate;
+    // Add the FP32 partial tile into the FP64 output: in four passes (one per
+    // 32-row block of every wave) the accumulators go through LDS and all 256
+    // threads then update C with coalesced row segments.
+    float *sC = (float *)smem;
+    constexpr int SROW = 129;
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float *sw = sC + wave * 32 * SROW;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    sw[((e >> 2) * 8 + lq + (e & 3)) * SROW + j * 32 + i32] = acc[i][j][e];
+                    acc[i][j][e] = 0.0f;
+                }
+            __syncthreads();
+#pragma unroll 2
+            for (int q = 0; q < 64; ++q) {
+                const int idx = tid + NT * q;
+                const int w = idx >> 12, rem = idx & 4095;
+                const int rl = rem >> 7, cl = rem & 127;
+                const int row = m0 + (w >> 1) * 128 + i * 32 + rl;
+                const int col = n0 + (w & 1) * 128 + cl;
+                if (row < M && col < N) {
+                    double *c = C + (size_t)row * ldc + col;
+                    double v = (double)sC[w * 32 * SROW + rl * SROW + cl];
+                    *c = first ? v : *c + v;
+                }
+            }
+            __syncthreads();
+        }
+        first = false;
+    };
+
+    gload(0);
+    for (int kc0 = 0; kc0 < K; kc0 += KC) {
+        const int kend = min(K, kc0 + KC);
+        for (int k0 = kc0; k0 < kend; k0 += BK) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                *(u4 *)(sAh + lr * LDK + 8 * q) = r[q];
+                *(u4 *)(sAl + lr * LDK + 8 * q) = r[NQ + q];
+                *(u4 *)(sBh + lr * LDK + 8 * q) = r[2 * NQ + q];
+                *(u4 *)(sBl + lr * LDK + 8 * q) = r[3 * NQ + q];
+            }
+            __syncthreads();
+            if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 16) {
+                bf16x8 bh[4], bl[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int col = wc * 128 + j * 32 + i32;
+                    bh[j] = *(const bf16x8 *)(sBh + col * LDK + ks + kh);
+                    bl[j] = *(const bf16x8 *)(sBl + col * LDK + ks + kh);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = wr * 128 + i * 32 + i32;
+                    const bf16x8 ah = *(const bf16x8 *)(sAh + row * LDK + ks + kh);
+                    const bf16x8 al = *(const bf16x8 *)(sAl + row * LDK + ks + kh);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        flush();  // FP32 chunk of at most KC k into the FP64 tile
+    }
+    if (first) flush();
+}
+}  // namespace x3
+
+void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl, double *C,
+                        int M, int N, int K, size_t lda, size_t ldb, size_t ldc, int accumulate, hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)x3::gemm_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)x3::LDS_BYTES);
+        attr_set = true;
+    }
+    int tm = (M + x3::BM - 1) / x3::BM, tn = (N + x3::BN - 1) / x3::BN;
+    x3::gemm_bf16x3_kernel<<<tm * tn, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, N, K, lda, ldb, ldc,
+                                                                   accumulate, tm, tn);
+}
+
+}  // namespace hotrg

@@ -1,0 +1,102 @@
+// Internal declarations shared by the HIP translation units of the HOTRG
+// library.  Nothing here is part of the public ABI (include/hotrg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace hotrg {
+
+// ---------------------------------------------------------------------------
+// Division by a run-time constant without a hardware divide: for n < 2^31 and
+// 1 <= d < 2^31, q = (umulhi(n, mul) + n) >> shift with
+// shift = ceil(log2 d), mul = floor(2^32 (2^shift - d) / d) + 1
+// (Granlund & Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994).
+// ---------------------------------------------------------------------------
+struct FastDiv {
+    uint32_t d, mul, shift;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    f.shift = s;
+    f.mul = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+    return f;
+}
+
+__device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv &f) {
+    return (__umulhi(n, f.mul) + n) >> f.shift;
+}
+
+// A strided multi-index map: output element o (row-major over ext[0..nd-1])
+// reads the input at sum_k coord_k * in_st[k] and a small matrix U at
+// sum_k coord_k * u_st[k]; the contracted index i adds i * in_sum_st and
+// i * u_sum_st.  All offsets are element offsets below 2^32.
+constexpr int MP_MAXD = 10;
+struct ModeParams {
+    int nd;
+    int nsum;
+    uint32_t total;
+    uint32_t in_sum_st, u_sum_st;
+    FastDiv ext[MP_MAXD];
+    uint32_t in_st[MP_MAXD];
+    uint32_t u_st[MP_MAXD];
+};
+
+constexpr int PERM_MAXD = 8;
+struct PermParams {
+    int nd;
+    uint32_t total;
+    FastDiv ext[PERM_MAXD];
+    uint32_t in_st[PERM_MAXD];
+};
+
+// ---- launchers (all asynchronous on `s`) ----------------------------------
+void launch_init_site(double *T, double *S, double w00, double w01, double w10, double w11,
+                      double v_up, double v_dn, hipStream_t s);
+void launch_permute(const PermParams &p, const double *in, double *out, double scale, hipStream_t s);
+void launch_mode_product(const ModeParams &p, const double *in, const double *U, double *out,
+                         hipStream_t s);
+void launch_mode_product_split(const ModeParams &p, const double *in, const double *U,
+                               uint16_t *hi, uint16_t *lo, hipStream_t s);
+// sum of squares of x[0..n) -> *out (device), deterministic two-pass reduction
+void launch_sumsq(const double *x, size_t n, double *partials, int npartials, double *out,
+                  hipStream_t s);
+// traces of up to 3 tensors with dims D[4] (legs x x' y y' z z' t t') and the
+// A matrix of Eq. (3.2) along `axis` of the first tensor.  out[0..2] traces,
+// out[3..3+D_axis^2) the A matrix.
+void launch_trace_obs(const double *T0, const double *T1, const double *T2, const int D[4],
+                      int axis, double *out, hipStream_t s);
+// G[(p, q), (p', q')] = sum_r X[p q r] X[p' q' r] for X given as R x K row-major
+// (R <= 144): split-K partials then a fixed-order reduction.
+void launch_gram(const double *X, int R, size_t K, double *partials, int nchunks, double *G,
+                 hipStream_t s);
+// E[(p, q), (p', q')] = sum_{a, a'} G1[p a p' a'] G2[q a q' a']
+void launch_env_combine(const double *G1, const double *G2, int Dp, int Dq, int Da, double *E,
+                        hipStream_t s);
+void launch_identity(double *U, int n, hipStream_t s);
+void launch_zero(double *x, size_t n, hipStream_t s);
+
+// Jacobi eigensolver: `count` symmetric n x n matrices (n <= 144) at A + i*n*n,
+// eigenvalues (descending) to lam + i*n, eigenvectors as columns of V + i*n*n
+// (row-major, V[r*n + j] = component r of vector j).  work: 2*count*n*n doubles.
+void launch_jacobi_eigh(const double *A, int n, int count, double *lam, double *V, double *work,
+                        int *sweeps, hipStream_t s);
+
+// C[M x N] (ldc) (+)= A[M x K] (lda) * B[N x K]^T (ldb); FP64 MFMA.
+void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, int K, size_t lda,
+                     size_t ldb, size_t ldc, int accumulate, hipStream_t s);
+// Same product from bf16 hi/lo splits: A ~ Ah + Al, B ~ Bh + Bl; computes
+// Ah Bh^T + Ah Bl^T + Al Bh^T with FP32 MFMA accumulation over chunks of at
+// most 2048 k, summed in FP64.  K must be a multiple of 32 (zero padded) and
+// lda, ldb multiples of 8.
+void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh,
+                        const uint16_t *Bl, double *C, int M, int N, int K, size_t lda, size_t ldb,
+                        size_t ldc, int accumulate, hipStream_t s);
+
+}  // namespace hotrg

@@ -1,0 +1,361 @@
+// Memory-bound tensor kernels of one HOTRG step on gfx950: initial tensors,
+// leg permutations, isometry (mode) products, norms, traces, Grams and the
+// squeezed environments.  All FP64; every reduction runs in a fixed order so
+// repeated runs are bitwise identical.
+#include "hotrg_internal.h"
+
+namespace hotrg {
+
+namespace {
+constexpr int kThreads = 256;
+
+inline int grid_for(size_t n, int per_block = kThreads, int cap = 65536) {
+    size_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (size_t)cap) g = cap;
+    return (int)g;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Initial tensors, Eqs. (2.2) and (2.6): entry i of the 2^8 array has leg k
+// index (i >> (7 - k)) & 1; T = sum_s v_s prod_k W[s, i_k], S = sum_s s v_s ...
+// ---------------------------------------------------------------------------
+__global__ void init_site_kernel(double *T, double *S, double w00, double w01, double w10,
+                                 double w11, double vu, double vd) {
+    int i = threadIdx.x;
+    double pu = vu, pd = vd;
+    for (int k = 0; k < 8; ++k) {
+        int b = (i >> (7 - k)) & 1;
+        pu *= b ? w01 : w00;
+        pd *= b ? w11 : w10;
+    }
+    T[i] = pu + pd;
+    S[i] = pu - pd;
+}
+
+void launch_init_site(double *T, double *S, double w00, double w01, double w10, double w11,
+                      double vu, double vd, hipStream_t s) {
+    init_site_kernel<<<1, 256, 0, s>>>(T, S, w00, w01, w10, w11, vu, vd);
+}
+
+// ---------------------------------------------------------------------------
+// Generic permutation / strided gather with a scale: out[o] = scale * in[map(o)].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) permute_kernel(PermParams p, const double *__restrict__ in,
+                                                           double *__restrict__ out, double scale) {
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.total; o += gridDim.x * blockDim.x) {
+        uint32_t rem = o, ib = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.ext[k]);
+            ib += (rem - q * p.ext[k].d) * p.in_st[k];
+            rem = q;
+        }
+        out[o] = scale * in[ib];
+    }
+}
+
+void launch_permute(const PermParams &p, const double *in, double *out, double scale, hipStream_t s) {
+    if (p.total == 0) return;
+    permute_kernel<<<grid_for(p.total), kThreads, 0, s>>>(p, in, out, scale);
+}
+
+// ---------------------------------------------------------------------------
+// Isometry (mode) product: out[o] = sum_i U[u(o) + i us] in[x(o) + i xs].
+// Consecutive threads produce consecutive outputs (coalesced stores); the
+// isometry is tiny and stays in L1/L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mp_offsets(const ModeParams &p, uint32_t o, uint32_t &ib, uint32_t &ub) {
+    uint32_t rem = o;
+    ib = 0;
+    ub = 0;
+    for (int k = p.nd - 1; k >= 0; --k) {
+        uint32_t q = fast_div(rem, p.ext[k]);
+        uint32_t c = rem - q * p.ext[k].d;
+        ib += c * p.in_st[k];
+        ub += c * p.u_st[k];
+        rem = q;
+    }
+}
+
+__device__ __forceinline__ double mp_sum(const ModeParams &p, const double *__restrict__ in,
+                                         const double *__restrict__ U, uint32_t ib, uint32_t ub) {
+    double acc = 0.0;
+    for (int i = 0; i < p.nsum; ++i) acc = fma(U[ub + i * p.u_sum_st], in[ib + i * p.in_sum_st], acc);
+    return acc;
+}
+
+__global__ void __launch_bounds__(kThreads) mode_product_kernel(ModeParams p, const double *__restrict__ in,
+                                                                const double *__restrict__ U,
+                                                                double *__restrict__ out) {
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.total; o += gridDim.x * blockDim.x) {
+        uint32_t ib, ub;
+        mp_offsets(p, o, ib, ub);
+        out[o] = mp_sum(p, in, U, ib, ub);
+    }
+}
+
+// bf16 round-to-nearest-even of a float (finite inputs), raw bits.
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ double bf16_value(uint16_t b) {
+    return (double)__uint_as_float(((uint32_t)b) << 16);
+}
+
+__global__ void __launch_bounds__(kThreads) mode_product_split_kernel(ModeParams p, const double *__restrict__ in,
+                                                                      const double *__restrict__ U,
+                                                                      uint16_t *__restrict__ hi,
+                                                                      uint16_t *__restrict__ lo) {
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.total; o += gridDim.x * blockDim.x) {
+        uint32_t ib, ub;
+        mp_offsets(p, o, ib, ub);
+        double a = mp_sum(p, in, U, ib, ub);
+        uint16_t h = bf16_bits((float)a);
+        uint16_t l = bf16_bits((float)(a - bf16_value(h)));
+        hi[o] = h;
+        lo[o] = l;
+    }
+}
+
+void launch_mode_product(const ModeParams &p, const double *in, const double *U, double *out, hipStream_t s) {
+    if (p.total == 0) return;
+    mode_product_kernel<<<grid_for(p.total), kThreads, 0, s>>>(p, in, U, out);
+}
+
+void launch_mode_product_split(const ModeParams &p, const double *in, const double *U, uint16_t *hi,
+                               uint16_t *lo, hipStream_t s) {
+    if (p.total == 0) return;
+    mode_product_split_kernel<<<grid_for(p.total), kThreads, 0, s>>>(p, in, U, hi, lo);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic sum of squares.
+// ---------------------------------------------------------------------------
+__device__ double block_sum(double v, double *sh) {
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kThreads) sumsq_partial_kernel(const double *__restrict__ x, size_t n,
+                                                                 double *__restrict__ partials) {
+    __shared__ double sh[kThreads];
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        acc = fma(x[i], x[i], acc);
+    double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(1024) sum_final_kernel(const double *__restrict__ partials, int n,
+                                                         double *__restrict__ out) {
+    __shared__ double sh[1024];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partials[i];
+    double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = r;
+}
+
+void launch_sumsq(const double *x, size_t n, double *partials, int npartials, double *out, hipStream_t s) {
+    int g = npartials;
+    sumsq_partial_kernel<<<g, kThreads, 0, s>>>(x, n, partials);
+    sum_final_kernel<<<1, 1024, 0, s>>>(partials, g, out);
+}
+
+// ---------------------------------------------------------------------------
+// Traces (Eq. (2.5)) and the A matrix of Eq. (3.2).
+// ---------------------------------------------------------------------------
+struct TraceDims {
+    int D[4];
+    uint32_t diag_st[4];  // stride of moving both legs of an axis by one
+    uint32_t leg_st[8];
+};
+
+__global__ void __launch_bounds__(kThreads) trace_obs_kernel(const double *__restrict__ T0,
+                                                             const double *__restrict__ T1,
+                                                             const double *__restrict__ T2, TraceDims td,
+                                                             int axis, double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    int b = blockIdx.x;
+    if (b < 3) {
+        const double *T = b == 0 ? T0 : (b == 1 ? T1 : T2);
+        if (!T) {
+            if (threadIdx.x == 0) out[b] = 0.0;
+            return;
+        }
+        uint32_t total = (uint32_t)td.D[0] * td.D[1] * td.D[2] * td.D[3];
+        double acc = 0.0;
+        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+            uint32_t rem = e, off = 0;
+            for (int q = 3; q >= 0; --q) {
+                off += (rem % td.D[q]) * td.diag_st[q];
+                rem /= td.D[q];
+            }
+            acc += T[off];
+        }
+        double r = block_sum(acc, sh);
+        if (threadIdx.x == 0) out[b] = r;
+        return;
+    }
+    // A[t, t'] for t, t' of `axis`; sum over the diagonals of the other axes
+    int e = b - 3;
+    int Da = td.D[axis];
+    int t = e / Da, tp = e % Da;
+    uint32_t base = t * td.leg_st[2 * axis] + tp * td.leg_st[2 * axis + 1];
+    uint32_t total = 1;
+    for (int q = 0; q < 4; ++q)
+        if (q != axis) total *= td.D[q];
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) {
+        uint32_t rem = i, off = base;
+        for (int q = 3; q >= 0; --q) {
+            if (q == axis) continue;
+            off += (rem % td.D[q]) * td.diag_st[q];
+            rem /= td.D[q];
+        }
+        acc += T0[off];
+    }
+    double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[3 + e] = r;
+}
+
+void launch_trace_obs(const double *T0, const double *T1, const double *T2, const int D[4], int axis,
+                      double *out, hipStream_t s) {
+    TraceDims td;
+    uint32_t st = 1;
+    for (int l = 7; l >= 0; --l) {
+        td.leg_st[l] = st;
+        st *= (uint32_t)D[l / 2];
+    }
+    for (int q = 0; q < 4; ++q) {
+        td.D[q] = D[q];
+        td.diag_st[q] = td.leg_st[2 * q] + td.leg_st[2 * q + 1];
+    }
+    int nblocks = 3 + D[axis] * D[axis];
+    trace_obs_kernel<<<nblocks, kThreads, 0, s>>>(T0, T1, T2, td, axis, out);
+}
+
+// ---------------------------------------------------------------------------
+// Gram of the rows of X (R x K, row-major): split-K partial products by a
+// 16 x 16 thread grid, each thread owning up to 9 x 9 outputs (R <= 144).
+// ---------------------------------------------------------------------------
+constexpr int GR_MAXB = 9;
+constexpr int GR_KB = 16;
+
+__global__ void __launch_bounds__(256) gram_partial_kernel(const double *__restrict__ X, int R, size_t K,
+                                                          size_t chunk, double *__restrict__ partials) {
+    __shared__ double Xs[144][GR_KB + 1];
+    const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
+    size_t k0 = (size_t)blockIdx.x * chunk;
+    size_t k1 = k0 + chunk < K ? k0 + chunk : K;
+    double acc[GR_MAXB][GR_MAXB];
+#pragma unroll
+    for (int a = 0; a < GR_MAXB; ++a)
+#pragma unroll
+        for (int b = 0; b < GR_MAXB; ++b) acc[a][b] = 0.0;
+    for (size_t kb = k0; kb < k1; kb += GR_KB) {
+        for (int idx = threadIdx.x; idx < R * GR_KB; idx += 256) {
+            int r = idx / GR_KB, kk = idx % GR_KB;
+            size_t k = kb + kk;
+            Xs[r][kk] = k < k1 ? X[(size_t)r * K + k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < GR_KB; ++kk) {
+            double xa[GR_MAXB], xb[GR_MAXB];
+#pragma unroll
+            for (int a = 0; a < GR_MAXB; ++a) {
+                int r = ti + 16 * a;
+                xa[a] = r < R ? Xs[r][kk] : 0.0;
+                int c = tj + 16 * a;
+                xb[a] = c < R ? Xs[c][kk] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < GR_MAXB; ++a)
+#pragma unroll
+                for (int b = 0; b < GR_MAXB; ++b) acc[a][b] = fma(xa[a], xb[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+    double *P = partials + (size_t)blockIdx.x * R * R;
+#pragma unroll
+    for (int a = 0; a < GR_MAXB; ++a)
+#pragma unroll
+        for (int b = 0; b < GR_MAXB; ++b) {
+            int r = ti + 16 * a, c = tj + 16 * b;
+            if (r < R && c < R) P[r * R + c] = acc[a][b];
+        }
+}
+
+__global__ void __launch_bounds__(kThreads) gram_reduce_kernel(const double *__restrict__ partials, int RR,
+                                                               int nchunks, double *__restrict__ G) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= RR) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunks; ++c) acc += partials[(size_t)c * RR + e];
+    G[e] = acc;
+}
+
+void launch_gram(const double *X, int R, size_t K, double *partials, int nchunks, double *G, hipStream_t s) {
+    size_t chunk = (K + nchunks - 1) / nchunks;
+    chunk = (chunk + GR_KB - 1) / GR_KB * GR_KB;
+    int used = (int)((K + chunk - 1) / chunk);
+    gram_partial_kernel<<<used, 256, 0, s>>>(X, R, K, chunk, partials);
+    gram_reduce_kernel<<<grid_for((size_t)R * R), kThreads, 0, s>>>(partials, R * R, used, G);
+}
+
+// ---------------------------------------------------------------------------
+// Squeezed environment E[(p q), (p' q')] = sum_{a a'} G1[p a p' a'] G2[q a q' a'].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) env_combine_kernel(const double *__restrict__ G1,
+                                                               const double *__restrict__ G2, int Dp, int Dq,
+                                                               int Da, double *__restrict__ E) {
+    int n = Dp * Dq;
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    int row = e / n, col = e % n;
+    int p = row / Dq, q = row % Dq, pp = col / Dq, qq = col % Dq;
+    int R1 = Dp * Da, R2 = Dq * Da;
+    double acc = 0.0;
+    for (int a = 0; a < Da; ++a)
+        for (int ap = 0; ap < Da; ++ap)
+            acc = fma(G1[(size_t)(p * Da + a) * R1 + pp * Da + ap], G2[(size_t)(q * Da + a) * R2 + qq * Da + ap],
+                      acc);
+    E[e] = acc;
+}
+
+void launch_env_combine(const double *G1, const double *G2, int Dp, int Dq, int Da, double *E, hipStream_t s) {
+    int n = Dp * Dq;
+    env_combine_kernel<<<grid_for((size_t)n * n), kThreads, 0, s>>>(G1, G2, Dp, Dq, Da, E);
+}
+
+__global__ void identity_kernel(double *U, int n) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n * n) U[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+void launch_identity(double *U, int n, hipStream_t s) {
+    identity_kernel<<<grid_for((size_t)n * n), kThreads, 0, s>>>(U, n);
+}
+
+__global__ void zero_kernel(double *x, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = 0.0;
+}
+
+void launch_zero(double *x, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    zero_kernel<<<grid_for(n), kThreads, 0, s>>>(x, n);
+}
+
+}  // namespace hotrg

@@ -1,0 +1,240 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Levels (every comparison uses gauge-invariant quantities or identical inputs):
+  * init: T^(0), S^(0) and lnZ/N at n = 0;
+  * contraction with caller-given isometries: full new tensors at small,
+    ragged dims (all four axes, both impurity pairings), sampled entries at
+    D = 8 (FP64 and bf16x3) and at D = 10 in the launch configuration the
+    benchmark times (bf16x3 with impurity rows);
+  * whole steps: spectra and projectors U U^T;
+  * whole flows: lnZ/N, <sigma>, <sigma sigma>, X per step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import hotrg as OH
+from oracle import sample as OS
+from tests import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_1906_06060_amd import hotrg
+    hotrg.load()
+    return hotrg
+
+
+def _dims_tensor_shape(dims):
+    s = []
+    for D in dims:
+        s += [D, D]
+    return tuple(s)
+
+
+# ------------------------------------------------------------------ init ----
+@pytest.mark.parametrize("beta,h", [(0.1497, 0.0), (0.3, 0.2), (0.0, 0.5), (1.2, -0.1)])
+def test_init_matches_oracle(H, beta, h):
+    f = OH.start(beta, h, 4, 4)
+    with H.Context(beta, h, 4) as ctx:
+        np.testing.assert_allclose(ctx.tensor(0), f.T, rtol=1e-15, atol=1e-16)
+        np.testing.assert_allclose(ctx.tensor(1), f.Sm, rtol=1e-15, atol=1e-16)
+        np.testing.assert_allclose(ctx.tensor(2), f.Se, rtol=1e-15, atol=1e-16)
+        ob = ctx.observables()
+    want = OH.observables(f, None)
+    assert ob["lnz_per_site"] == pytest.approx(want["lnz_per_site"], rel=1e-14)
+    assert ob["m_imp"] == pytest.approx(math.tanh(beta * h), rel=1e-13, abs=1e-15)
+
+
+# ------------------------------------- contraction on identical inputs ----
+CASES = [
+    # dims, dcut, axis, ks per transverse axis (None = min(dcut, D^2))
+    ((2, 2, 2, 2), 4, 0, None),
+    ((4, 3, 2, 4), 4, 3, None),
+    ((4, 3, 2, 4), 4, 1, None),
+    ((3, 5, 2, 4), 5, 2, None),
+    ((3, 5, 2, 4), 5, 0, (2, 1, 3)),
+    ((1, 2, 3, 1), 3, 3, None),
+]
+
+
+@pytest.mark.parametrize("dims,dcut,axis,ks", CASES)
+@pytest.mark.parametrize("n0", [0, 3])
+def test_contraction_full_tensor_fp64(H, dims, dcut, axis, ks, n0):
+    T = synth.z2_tensor(dims, seed=101)
+    Sm = synth.z2_tensor(dims, seed=102, odd=True)
+    Se = synth.z2_tensor(dims, seed=103)
+    tv = [q for q in range(4) if q != axis]
+    Us = {}
+    for j, q in enumerate(tv):
+        n = dims[q] ** 2
+        k = min(dcut, n) if ks is None else ks[j]
+        Us[q] = synth.isometry(n, k, seed=200 + q)
+    with H.Context(0.2, 0.0, dcut) as ctx:
+        ctx.set_state(T, Sm, Se, n=n0, lnz_acc=0.0)
+        ctx.step_with_isometries(axis, Us)
+        got = [ctx.tensor(w) for w in range(3)]
+        ob = ctx.observables()
+    want_T = OH.coarse_grain(T, T, Us, axis)
+    c = np.linalg.norm(want_T)
+    want = [want_T / c, OH.coarse_grain(Sm, T, Us, axis) / c,
+            OH.coarse_grain(Se, Se if n0 == 0 else T, Us, axis) / c]
+    assert ob["last_cn"] == pytest.approx(c, rel=1e-13)
+    for g, w in zip(got, want):
+        assert g.shape == w.shape
+        np.testing.assert_allclose(g, w, rtol=0, atol=1e-13 * max(np.abs(w).max(), 1e-300))
+
+
+def _sampled_parity(H, D, axis, precision, impurities, nrows, bound, seed=7):
+    dims = (D, D, D, D)
+    T = synth.z2_tensor(dims, seed=seed)
+    Sm = synth.z2_tensor(dims, seed=seed + 1, odd=True) if impurities else None
+    Se = synth.z2_tensor(dims, seed=seed + 2) if impurities else None
+    tv = [q for q in range(4) if q != axis]
+    Us = {q: synth.isometry(D * D, D, seed=seed + 10 + q) for q in tv}
+    with H.Context(0.2, 0.0, D, precision=precision, impurities=impurities, mixed_from_step=1) as ctx:
+        ctx.set_state(T, Sm, Se, n=4, lnz_acc=0.0)
+        ctx.step_with_isometries(axis, Us)
+        cn = ctx.observables()["last_cn"]
+        got = [ctx.tensor(w) for w in (range(3) if impurities else range(1))]
+    rshape = (D, D, D, D)
+    rows = synth.sample_indices(rshape, nrows, seed=seed + 20)
+    cols = synth.sample_indices(rshape, nrows, seed=seed + 21)
+    pairs = [(T, T)] + ([(Sm, T), (Se, T)] if impurities else [])
+    worst = 0.0
+    for (T1, T2), G in zip(pairs, got):
+        ent, rn, cnorm = OS.step_entries_with_norms(T1, T2, Us, axis, rows, cols)
+        for i, r in enumerate(rows):
+            for j, cc in enumerate(cols):
+                idx = [0] * 8
+                for q_i, q in enumerate(tv):
+                    idx[2 * q], idx[2 * q + 1] = r[q_i], cc[q_i]
+                idx[2 * axis], idx[2 * axis + 1] = r[-1], cc[-1]
+                err = abs(G[tuple(idx)] * cn - ent[i, j]) / (rn[i] * cnorm[j])
+                worst = max(worst, err)
+    assert worst <= bound, worst
+    return worst
+
+
+@pytest.mark.parametrize("axis", [3, 0])
+def test_contraction_sampled_d8_fp64(H, axis):
+    _sampled_parity(H, 8, axis, H.FP64, True, 24, 1e-13)
+
+
+@pytest.mark.parametrize("axis", [3, 1])
+def test_contraction_sampled_d8_bf16x3(H, axis):
+    # bf16x3: |a - hi - lo| <= 2^-16 |a|; dropping lo*lo and the residuals
+    # gives <= 3 * 2^-16 per product relative to |a||b|, plus FP32 sums inside
+    # chunks of 8192 k: bounded by 6e-5 |row| |col| (Cauchy-Schwarz)
+    w = _sampled_parity(H, 8, axis, H.BF16X3, True, 24, 6e-5)
+    print(f"bf16x3 D=8 worst scaled error {w:.3e}")
+
+
+def test_contraction_sampled_d10_bf16x3_bench_configuration(H):
+    w = _sampled_parity(H, 10, 3, H.BF16X3, True, 10, 6e-5, seed=31)
+    print(f"bf16x3 D=10 worst scaled error {w:.3e}")
+
+
+# ---------------------------------------------------------- whole steps ----
+def test_step_spectra_and_projectors_match_oracle(H):
+    beta, h, dcut = 0.1497, 0.0, 4
+    f = OH.start(beta, h, dcut, 4)
+    with H.Context(beta, h, dcut) as ctx:
+        for n in range(6):
+            axis = n % 4
+            ctx.step(axis)
+            rec = OH.step(f, axis)
+            for dec in rec.decisions:
+                q = dec.nu
+                if not dec.truncated:
+                    continue
+                for side in (0, 1):
+                    sg = ctx.spectrum(q, side)
+                    so = dec.spectra[side]
+                    l1 = so[0]
+                    np.testing.assert_allclose(sg / l1, so / l1, rtol=0, atol=1e-13)
+                Ug = ctx.isometry(q)
+                assert Ug.shape[1] == dec.k
+                np.testing.assert_allclose(Ug.T @ Ug, np.eye(dec.k), atol=1e-13)
+            ob = ctx.observables()
+            assert ob["lnz_per_site"] == pytest.approx(rec.lnz_per_site, rel=1e-12)
+
+
+def test_isometry_projector_matches_oracle(H):
+    # identical input tensor at every step (the oracle's state is loaded into
+    # the GPU context), so U U^T is gauge invariant and must agree
+    beta, h, dcut = 0.2, 0.003, 4
+    f = OH.start(beta, h, dcut, 4)
+    with H.Context(beta, h, dcut) as ctx:
+        for n in range(5):
+            axis = n % 4
+            ctx.set_state(f.T, f.Sm, f.Se, n=f.n, lnz_acc=f.lnz_acc)
+            Us, _, decs = OH.isometries(f.T, axis, dcut, f.labels)
+            ctx.step(axis)
+            ob = ctx.observables()
+            for dec in decs:
+                if dec.truncated:
+                    assert ob["last_side"][dec.nu] == dec.side
+                    assert ob["last_k"][dec.nu] == dec.k
+            for q, U in Us.items():
+                Ug = ctx.isometry(q)
+                np.testing.assert_allclose(Ug @ Ug.T, U @ U.T, atol=1e-10)
+            OH.step(f, axis)
+            assert ob["lnz_per_site"] == pytest.approx(f.records[-1].lnz_per_site, rel=1e-12)
+
+
+# ----------------------------------------------------------- whole flows ----
+def _compare_flow(H, beta, h, dcut, nsteps, rel=1e-10, **kw):
+    f = OH.run(beta, h, dcut, 4, nsteps)
+    got = H.flow(beta, h, dcut, nsteps, **kw)
+    for g, r in zip(got, f.records):
+        assert g["dims"] == r.dims
+        assert g["lnz_per_site"] == pytest.approx(r.lnz_per_site, rel=rel)
+        assert g["m_imp"] == pytest.approx(r.m_imp, rel=1e-8, abs=1e-12)
+        assert g["nn_imp"] == pytest.approx(r.nn_imp, rel=1e-8)
+        assert g["X"] == pytest.approx(r.X, rel=1e-8)
+    return got, f
+
+
+def test_flow_c1_dcut4_matches_oracle(H):
+    # beta = 0.1497, h = 0, Dcut = 4, 16 steps cycling x, y, z, t (16^4 sites)
+    got, f = _compare_flow(H, 0.1497, 0.0, 4, 16)
+    for g in got:
+        assert g["m_imp"] == 0.0          # Z2 kept exactly at h = 0
+
+
+@pytest.mark.parametrize("beta,h", [(0.16, 0.01), (0.12, 1e-4)])
+def test_flow_with_field_matches_oracle(H, beta, h):
+    _compare_flow(H, beta, h, 4, 10)
+
+
+@pytest.mark.parametrize("dcut", [1, 2, 3, 5])
+def test_flow_other_dcut_matches_oracle(H, dcut):
+    _compare_flow(H, 0.15, 0.02, dcut, 8)
+
+
+def test_beta_zero_is_ln2(H):
+    for g in H.flow(0.0, 0.0, 4, 8):
+        assert g["lnz_per_site"] == pytest.approx(math.log(2.0), abs=1e-14)
+
+
+def test_bitwise_repeatable(H):
+    a = H.flow(0.15, 0.0, 4, 6)
+    b = H.flow(0.15, 0.0, 4, 6)
+    assert [x["lnz_per_site"] for x in a] == [x["lnz_per_site"] for x in b]
+
+
+def test_step_errors(H):
+    with H.Context(0.15, 0.0, 4) as ctx:
+        with pytest.raises(H.HotrgError) as e:
+            ctx.step(4)
+        assert e.value.code == H.EINVAL
+        ctx.step(0)
+        with pytest.raises(H.HotrgError):
+            ctx.isometry(0)
