@@ -1,0 +1,164 @@
+"""Benchmark: steady-state HOTRG step of the 4D Ising model on one MI355X.
+
+Workload (the metric's configuration): Dcut = 10, h = 0, beta = 0.14968 (a
+point of the 16-point scan in [0.1494, 0.1500]), bf16x3 contraction with FP64
+environments / eigh / norms, impurity tensors S_m and S_e carried, so every
+step contracts M = 3 * 10^4 operand rows against N = 10^4 columns over
+K = 10^7 (2 M N K = 6.0e15 algorithmic flops).  Steps 1-3 (bond dims ramping
+up to 10) run untimed; W warm-up steps follow; then exactly K steps are timed
+with a device synchronisation on both sides.
+
+Prints one JSON line.  --precision fp64 times the plain FP64 path instead.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16 = 2.5e15     # MI355X dense bf16 MFMA, flop/s
+PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--dcut", type=int, default=10)
+    p.add_argument("--beta", type=float, default=0.14968)
+    p.add_argument("--h", type=float, default=0.0)
+    p.add_argument("--precision", choices=["bf16x3", "fp64"], default="bf16x3")
+    p.add_argument("--no-impurities", action="store_true")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-rows", type=int, default=12)
+    return p.parse_args()
+
+
+def cpu_baseline(dcut, rows):
+    """The CPU oracle on a bounded sample of the same step: `rows` x `rows`
+    entries of the new tensor of a D = dcut step, each from its definition
+    (oracle.sample), on seeded Z2 inputs of the same shape.  Reported as the
+    algorithmic flop rate 2 K per entry (K = D^7)."""
+    import numpy as np
+    from oracle import sample as OS
+    from tests import synth
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        threads = max(i.get("num_threads", 1) for i in info) if info else os.cpu_count()
+    except Exception:
+        threads = os.cpu_count()
+    D = dcut
+    T = synth.z2_tensor((D, D, D, D), seed=5)
+    Us = {q: synth.isometry(D * D, D, seed=50 + q) for q in range(3)}
+    rs = synth.sample_indices((D, D, D, D), rows, seed=60)
+    cs = synth.sample_indices((D, D, D, D), rows, seed=61)
+    t0 = time.perf_counter()
+    OS.step_entries(T, T, Us, 3, rs, cs)
+    dt = time.perf_counter() - t0
+    K = D ** 7
+    flops = 2.0 * rows * rows * K
+    return {
+        "value": flops / dt / 1e12,
+        "unit": "TFLOP/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{rows}x{rows} entries of one D={D} step (K={K}) from the definition, "
+                  f"seeded Z2 inputs; {dt:.1f} s; projected full pure step "
+                  f"{dt * (D ** 4) ** 2 / rows ** 2:.3g} s",
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from paper_1906_06060_amd import hotrg as H
+    prec = H.BF16X3 if a.precision == "bf16x3" else H.FP64
+    imp = not a.no_impurities
+    D = a.dcut
+    ctx = H.Context(a.beta, a.h, D, precision=prec, impurities=imp)
+    axis = 0
+    t_setup = time.perf_counter()
+    for _ in range(3):                      # ramp-up steps (dims grow to Dcut)
+        ctx.step(axis % 4)
+        axis += 1
+    for _ in range(a.warmup):
+        ctx.step(axis % 4)
+        axis += 1
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    dims, _ = ctx.dims()
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ctx.step(axis % 4)
+        axis += 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ob = ctx.observables()
+    st = ctx.gemm_stats()
+    ctx.close()
+
+    rows = (3 if imp else 1) * D ** 4
+    step_flops = 2.0 * rows * D ** 4 * D ** 7
+    sec = elapsed / a.steps
+    tflops = step_flops / sec / 1e12
+    peak = PEAK_BF16 if prec == H.BF16X3 else PEAK_FP64
+    issue = 3.0 if prec == H.BF16X3 else 1.0
+    gemm_s = st["ms"] / 1e3
+    achieved = st["flops"] / gemm_s if gemm_s > 0 else float("nan")
+    line = {
+        "metric": "HOTRG step time & TFLOP/s (% MFMA peak) at Dcut=10, mixed vs FP64",
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(sec * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3" if prec == H.BF16X3 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"4D Ising HOTRG steady-state step, Dcut={D}, "
+                        f"{'bf16x3' if prec == H.BF16X3 else 'fp64'} contraction, "
+                        f"{'T+S_m+S_e rows' if imp else 'T rows'} (M={rows}, N={D ** 4}, K={D ** 7})",
+            "beta": a.beta, "h": a.h, "dcut": D, "dims": list(dims),
+            "step_flops": step_flops, "pct_mfma_peak_issued": round(100 * issue * tflops * 1e12 / peak, 2),
+            "setup_s": round(setup_s, 2),
+            "lnz_per_site": ob["lnz_per_site"], "nn_imp": ob["nn_imp"], "m_imp": ob["m_imp"], "X": ob["X"],
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "gemm_bf16x3_kernel" if prec == H.BF16X3 else "gemm_f64_kernel",
+            "achieved": round(achieved / 1e12, 3),
+            "peak": peak / 1e12,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "issued_frac": round(issue * achieved / peak, 4),
+            "traffic": None,
+            "launches": st["launches"],
+            "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 3),
+        },
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(D, a.cpu_rows)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

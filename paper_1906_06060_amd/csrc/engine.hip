@@ -212,6 +212,96 @@ struct MP {
     }
 };
 
+// Vectorised mode product description (see VecModeParams).
+struct VM {
+    VecModeParams p{};
+    uint64_t outer = 1, max_in = 0, max_u = 0;
+    bool both_j = false;
+    void dim(int ext, uint64_t ist, uint64_t ust) {
+        int k = p.nd++;
+        if (k >= MP_MAXD) return;
+        p.ext[k] = make_fastdiv((uint32_t)ext);
+        p.in_st[k] = (uint32_t)ist;
+        p.u_st[k] = (uint32_t)ust;
+        outer *= (uint64_t)ext;
+        max_in += (uint64_t)(ext - 1) * ist;
+        max_u += (uint64_t)(ext - 1) * ust;
+    }
+    void jdim(int J, uint64_t xj, uint64_t uj) {
+        p.J = J;
+        p.xj = (uint32_t)xj;
+        p.uj = (uint32_t)uj;
+        both_j = xj != 0 && uj != 0;
+        max_in += (uint64_t)(J - 1) * xj;
+        max_u += (uint64_t)(J - 1) * uj;
+    }
+    void sum(int n, uint64_t xs, uint64_t us) {
+        p.nsum = n;
+        p.xs = (uint32_t)xs;
+        p.us = (uint32_t)us;
+        max_in += (uint64_t)(n - 1) * xs;
+        max_u += (uint64_t)(n - 1) * us;
+    }
+    // host-side bounds check (elements available from each base pointer)
+    bool fits(uint64_t in_avail, uint64_t u_avail, uint64_t out_avail) const {
+        const uint64_t total = outer * (uint64_t)p.J;
+        return p.nd <= MP_MAXD && p.J >= 1 && p.J <= VM_MAXJ && p.nsum >= 1 && p.nsum <= VM_MAXJ && !both_j &&
+               total < (1ull << 31) && max_in < in_avail && max_in < (1ull << 32) && max_u < u_avail &&
+               total <= out_avail;
+    }
+    const VecModeParams &done() {
+        p.outer_total = (uint32_t)outer;
+        return p;
+    }
+};
+
+// Isometry expand-product description (see ExpandParams).
+struct XP {
+    ExpandParams p{};
+    uint64_t threads = 1, max_in = 0, max_u = 0, max_out = 0;
+    bool bad = false;
+    void tdim(int ext, uint64_t ist, uint64_t ost) {
+        if (p.nd >= XP_MAXD) {
+            bad = true;
+            return;
+        }
+        int k = p.nd++;
+        p.ext[k] = make_fastdiv((uint32_t)ext);
+        p.in_st[k] = (uint32_t)ist;
+        p.out_st[k] = (uint32_t)ost;
+        threads *= (uint64_t)ext;
+        max_in += (uint64_t)(ext - 1) * ist;
+        max_out += (uint64_t)(ext - 1) * ost;
+    }
+    void loops(int L1, uint64_t u1, uint64_t o1, int L2, uint64_t u2, uint64_t o2) {
+        p.L1 = L1;
+        p.L2 = L2;
+        p.u1 = (uint32_t)u1;
+        p.o1 = (uint32_t)o1;
+        p.u2 = (uint32_t)u2;
+        p.o2 = (uint32_t)o2;
+        max_u += (uint64_t)(L1 - 1) * u1 + (uint64_t)(L2 - 1) * u2;
+        max_out += (uint64_t)(L1 - 1) * o1 + (uint64_t)(L2 - 1) * o2;
+    }
+    void sum(int n, uint64_t xs, uint64_t us) {
+        p.nsum = n;
+        p.xs = (uint32_t)xs;
+        p.us = (uint32_t)us;
+        max_in += (uint64_t)(n - 1) * xs;
+        max_u += (uint64_t)(n - 1) * us;
+    }
+    // host-side bounds check (elements available from each base pointer)
+    bool fits(uint64_t in_avail, uint64_t u_avail, uint64_t out_avail) const {
+        return !bad && p.nsum >= 1 && p.nsum <= XP_MAXS && p.L1 >= 1 && p.L2 >= 1 && p.L2 <= XP_MAXS &&
+               threads < (1ull << 31) && max_in < in_avail && max_in < (1ull << 32) && max_u < u_avail &&
+               max_out < out_avail && max_out < (1ull << 32);
+    }
+    const ExpandParams &done() {
+        p.threads = (uint32_t)threads;
+        return p;
+    }
+};
+
 void row_major_strides(int nd, const int *ext, uint64_t *st) {
     uint64_t s = 1;
     for (int k = nd - 1; k >= 0; --k) {
@@ -434,123 +524,127 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     const uint64_t tsize = tensor_size(D);
     c->ev_used = 0;
 
-    // intermediate strides
-    const int y1e[7] = {ka, Da, Db, Db, Dc, Dc, Dm};
+    // Intermediate layouts (the index summed next is innermost, the GEMM row
+    // part outermost in GEMM order, so every read is a contiguous run):
+    //   Y1[a, mu1, b1', c1', a2, c1, b1]        Y2[a, b, mu1, b1', c1', a2, b2, c1]
+    //   Z1[a', mu2', a2, b2, c2, c2', b2']      Z2[a', b', mu2', b1', a2, b2, c2, c2']
+    // GEMM rows (a, b, mu1, c), columns (a', b', mu2', c'), K (b1', c1', a2, b2, c2).
+    const int y1e[7] = {ka, Dm, Db, Dc, Da, Dc, Db};
     uint64_t y1s[7];
     row_major_strides(7, y1e, y1s);
-    const int y2e[8] = {ka, Da, kb, Db, Db, Dc, Dc, Dm};
+    const int y2e[8] = {ka, kb, Dm, Db, Dc, Da, Db, Dc};
     uint64_t y2s[8];
     row_major_strides(8, y2e, y2s);
-    // Q-side intermediates use the same extents pattern
-    const int z1e[7] = {ka, Da, Db, Db, Dc, Dc, Dm};
+    const int z1e[7] = {ka, Dm, Da, Db, Dc, Dc, Db};
     uint64_t z1s[7];
     row_major_strides(7, z1e, z1s);
-    const int z2e[8] = {ka, Da, kb, Db, Db, Dc, Dc, Dm};
+    const int z2e[8] = {ka, kb, Dm, Db, Da, Db, Dc, Dc};
     uint64_t z2s[8];
     row_major_strides(8, z2e, z2s);
+
+    // K-part strides of an operand row (b1', c1', a2, b2, c2) and row strides
+    const uint64_t ks0 = (uint64_t)Dc * Da * Db * Dc, ks1 = (uint64_t)Da * Db * Dc, ks2 = (uint64_t)Db * Dc,
+                   ks3 = Dc;
+    const uint64_t rs0 = (uint64_t)kb * Dm * kc * Ks, rs1 = (uint64_t)Dm * kc * Ks, rs2 = (uint64_t)kc * Ks;
 
     bool first_slice = true;
     for (int g = 0; g < Dm; ++g) {       // alpha
         for (int f = 0; f < Da; ++f) {   // a1'
             // ---- A rows: T1 in {T, S_m, S_e}
             for (int t = 0; t < nA; ++t) {
-                const double *X1 = c->state[t] + f * lst[1] + g * lst[7];
-                {   // P1: Y1[a,a2,b1,b1',c1,c1',mu1] = sum_a1 Ua[(a1,a2),a] X1[a1,f,b1,b1',c1,c1',mu1,g]
-                    MP m;
-                    m.dim(ka, 0, 1);
-                    m.dim(Da, 0, ka);
-                    m.dim(Db, lst[2], 0);
-                    m.dim(Db, lst[3], 0);
-                    m.dim(Dc, lst[4], 0);
-                    m.dim(Dc, lst[5], 0);
-                    m.dim(Dm, lst[6], 0);
-                    m.sum(Da, lst[0], (uint64_t)Da * ka);
-                    if (!m.fits(tsize - (f * lst[1] + g * lst[7]), usz[0], c->cap))
-                        return set_err(HOTRG_EINVAL, "P1 launch out of bounds");
-                    launch_mode_product(m.done(), X1, Ua, c->y1, c->stream);
+                const uint64_t off = f * lst[1] + g * lst[7];
+                const double *X1 = c->state[t] + off;
+                {   // P1: Y1[a,mu1,b1',c1',a2,c1,b1] = sum_a1 Ua[(a1,a2),a] T1[a1,f,b1,b1',c1,c1',mu1,g]
+                    XP x;
+                    x.tdim(Dm, lst[6], y1s[1]);
+                    x.tdim(Db, lst[3], y1s[2]);
+                    x.tdim(Dc, lst[5], y1s[3]);
+                    x.tdim(Dc, lst[4], y1s[5]);
+                    x.tdim(Db, lst[2], y1s[6]);
+                    x.loops(ka, 1, y1s[0], Da, ka, y1s[4]);
+                    x.sum(Da, lst[0], (uint64_t)Da * ka);
+                    if (!x.fits(tsize - off, usz[0], c->cap)) return set_err(HOTRG_EINVAL, "P1 launch out of bounds");
+                    launch_iso_expand(x.done(), X1, Ua, c->y1, nullptr, nullptr, c->stream);
                 }
-                {   // P2: Y2[a,a2,b,b2,b1',c1,c1',mu1] = sum_b1 Ub[(b1,b2),b] Y1[a,a2,b1,b1',c1,c1',mu1]
-                    MP m;
-                    m.dim(ka, y1s[0], 0);
-                    m.dim(Da, y1s[1], 0);
-                    m.dim(kb, 0, 1);
-                    m.dim(Db, 0, kb);
-                    m.dim(Db, y1s[3], 0);
-                    m.dim(Dc, y1s[4], 0);
-                    m.dim(Dc, y1s[5], 0);
-                    m.dim(Dm, y1s[6], 0);
-                    m.sum(Db, y1s[2], (uint64_t)Db * kb);
-                    if (!m.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "P2 launch out of bounds");
-                    launch_mode_product(m.done(), c->y1, Ub, c->y2, c->stream);
+                {   // P2: Y2[a,b,mu1,b1',c1',a2,b2,c1] = sum_b1 Ub[(b1,b2),b] Y1
+                    XP x;
+                    x.tdim(ka, y1s[0], y2s[0]);
+                    x.tdim(Dm, y1s[1], y2s[2]);
+                    x.tdim(Db, y1s[2], y2s[3]);
+                    x.tdim(Dc, y1s[3], y2s[4]);
+                    x.tdim(Da, y1s[4], y2s[5]);
+                    x.tdim(Dc, y1s[5], y2s[7]);
+                    x.loops(kb, 1, y2s[1], Db, kb, y2s[6]);
+                    x.sum(Db, y1s[6], (uint64_t)Db * kb);
+                    if (!x.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "P2 launch out of bounds");
+                    launch_iso_expand(x.done(), c->y1, Ub, c->y2, nullptr, nullptr, c->stream);
                 }
-                {   // P3: A[(a,b,c,mu1),(b1',c1',a2,b2,c2)] = sum_c1 Uc[(c1,c2),c] Y2[a,a2,b,b2,b1',c1,c1',mu1]
-                    MP m;
-                    m.dim(ka, y2s[0], 0);
-                    m.dim(kb, y2s[2], 0);
-                    m.dim(kc, 0, 1);
-                    m.dim(Dm, y2s[7], 0);
-                    m.dim(Db, y2s[4], 0);
-                    m.dim(Dc, y2s[6], 0);
-                    m.dim(Da, y2s[1], 0);
-                    m.dim(Db, y2s[3], 0);
-                    m.dim(Dc, 0, kc);
-                    m.sum(Dc, y2s[5], (uint64_t)Dc * kc);
-                    if (!m.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
+                {   // P3: A[(a,b,mu1,c),(b1',c1',a2,b2,c2)] = sum_c1 Uc[(c1,c2),c] Y2
+                    XP x;
+                    x.tdim(ka, y2s[0], rs0);
+                    x.tdim(kb, y2s[1], rs1);
+                    x.tdim(Dm, y2s[2], rs2);
+                    x.tdim(Db, y2s[3], ks0);
+                    x.tdim(Dc, y2s[4], ks1);
+                    x.tdim(Da, y2s[5], ks2);
+                    x.tdim(Db, y2s[6], ks3);
+                    x.loops(kc, 1, Ks, Dc, kc, 1);
+                    x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
+                    if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
                     if (mixed)
-                        launch_mode_product_split(m.done(), c->y2, Uc, Ah + slice * t, Al + slice * t, c->stream);
+                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, Ah + slice * t, Al + slice * t, c->stream);
                     else
-                        launch_mode_product(m.done(), c->y2, Uc, Asl + slice * t, c->stream);
+                        launch_iso_expand(x.done(), c->y2, Uc, Asl + slice * t, nullptr, nullptr, c->stream);
                 }
             }
             // ---- B columns: T2 = T (and S_e for the first-step pair)
             for (int bidx = 0; bidx < nB; ++bidx) {
-                const double *X2 = c->state[bidx == 0 ? 0 : 2] + g * lst[6];
-                {   // Q1: Z1[a',a2,b2,b2',c2,c2',mu2'] = sum_a2' Ua[(f,a2'),a'] X2[a2,a2',b2,b2',c2,c2',g,mu2']
-                    MP m;
-                    m.dim(ka, 0, 1);
-                    m.dim(Da, lst[0], 0);
-                    m.dim(Db, lst[2], 0);
-                    m.dim(Db, lst[3], 0);
-                    m.dim(Dc, lst[4], 0);
-                    m.dim(Dc, lst[5], 0);
-                    m.dim(Dm, lst[7], 0);
-                    m.sum(Da, lst[1], ka);
-                    if (!m.fits(tsize - g * lst[6], usz[0] - (uint64_t)f * Da * ka, c->cap))
+                const uint64_t off = g * lst[6];
+                const double *X2 = c->state[bidx == 0 ? 0 : 2] + off;
+                {   // Q1: Z1[a',mu2',a2,b2,c2,c2',b2'] = sum_a2' Ua[(f,a2'),a'] T2[a2,a2',b2,b2',c2,c2',g,mu2']
+                    XP x;
+                    x.tdim(Dm, lst[7], z1s[1]);
+                    x.tdim(Da, lst[0], z1s[2]);
+                    x.tdim(Db, lst[2], z1s[3]);
+                    x.tdim(Dc, lst[4], z1s[4]);
+                    x.tdim(Dc, lst[5], z1s[5]);
+                    x.tdim(Db, lst[3], z1s[6]);
+                    x.loops(ka, 1, z1s[0], 1, 0, 0);
+                    x.sum(Da, lst[1], ka);
+                    if (!x.fits(tsize - off, usz[0] - (uint64_t)f * Da * ka, c->cap))
                         return set_err(HOTRG_EINVAL, "Q1 launch out of bounds");
-                    launch_mode_product(m.done(), X2, Ua + (size_t)f * Da * ka, c->y1, c->stream);
+                    launch_iso_expand(x.done(), X2, Ua + (size_t)f * Da * ka, c->y1, nullptr, nullptr, c->stream);
                 }
-                {   // Q2: Z2[a',a2,b',b1',b2,c2,c2',mu2'] = sum_b2' Ub[(b1',b2'),b'] Z1[a',a2,b2,b2',c2,c2',mu2']
-                    MP m;
-                    m.dim(ka, z1s[0], 0);
-                    m.dim(Da, z1s[1], 0);
-                    m.dim(kb, 0, 1);
-                    m.dim(Db, 0, (uint64_t)Db * kb);
-                    m.dim(Db, z1s[2], 0);
-                    m.dim(Dc, z1s[4], 0);
-                    m.dim(Dc, z1s[5], 0);
-                    m.dim(Dm, z1s[6], 0);
-                    m.sum(Db, z1s[3], kb);
-                    if (!m.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "Q2 launch out of bounds");
-                    launch_mode_product(m.done(), c->y1, Ub, c->y2, c->stream);
+                {   // Q2: Z2[a',b',mu2',b1',a2,b2,c2,c2'] = sum_b2' Ub[(b1',b2'),b'] Z1
+                    XP x;
+                    x.tdim(ka, z1s[0], z2s[0]);
+                    x.tdim(Dm, z1s[1], z2s[2]);
+                    x.tdim(Da, z1s[2], z2s[4]);
+                    x.tdim(Db, z1s[3], z2s[5]);
+                    x.tdim(Dc, z1s[4], z2s[6]);
+                    x.tdim(Dc, z1s[5], z2s[7]);
+                    x.loops(kb, 1, z2s[1], Db, (uint64_t)Db * kb, z2s[3]);
+                    x.sum(Db, z1s[6], kb);
+                    if (!x.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "Q2 launch out of bounds");
+                    launch_iso_expand(x.done(), c->y1, Ub, c->y2, nullptr, nullptr, c->stream);
                 }
-                {   // Q3: Bt[(a',b',c',mu2'),(b1',c1',a2,b2,c2)] = sum_c2' Uc[(c1',c2'),c'] Z2[a',a2,b',b1',b2,c2,c2',mu2']
-                    MP m;
-                    m.dim(ka, z2s[0], 0);
-                    m.dim(kb, z2s[2], 0);
-                    m.dim(kc, 0, 1);
-                    m.dim(Dm, z2s[7], 0);
-                    m.dim(Db, z2s[3], 0);
-                    m.dim(Dc, 0, (uint64_t)Dc * kc);
-                    m.dim(Da, z2s[1], 0);
-                    m.dim(Db, z2s[4], 0);
-                    m.dim(Dc, z2s[5], 0);
-                    m.sum(Dc, z2s[6], kc);
-                    if (!m.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
+                {   // Q3: Bt[(a',b',mu2',c'),(b1',c1',a2,b2,c2)] = sum_c2' Uc[(c1',c2'),c'] Z2
+                    XP x;
+                    x.tdim(ka, z2s[0], rs0);
+                    x.tdim(kb, z2s[1], rs1);
+                    x.tdim(Dm, z2s[2], rs2);
+                    x.tdim(Db, z2s[3], ks0);
+                    x.tdim(Da, z2s[4], ks2);
+                    x.tdim(Db, z2s[5], ks3);
+                    x.tdim(Dc, z2s[6], 1);
+                    x.loops(kc, 1, Ks, Dc, (uint64_t)Dc * kc, ks1);
+                    x.sum(Dc, z2s[7], kc);
+                    if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
                     if (mixed)
-                        launch_mode_product_split(m.done(), c->y2, Uc, Bh + slice * bidx, Bl + slice * bidx,
-                                                  c->stream);
+                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, Bh + slice * bidx, Bl + slice * bidx,
+                                          c->stream);
                     else
-                        launch_mode_product(m.done(), c->y2, Uc, Bsl + slice * bidx, c->stream);
+                        launch_iso_expand(x.done(), c->y2, Uc, Bsl + slice * bidx, nullptr, nullptr, c->stream);
                 }
             }
             // ---- GEMMs: C rows (+)= A B^T
@@ -600,22 +694,18 @@ int finish_step(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
         return set_err(HOTRG_ENUMERIC, "norm of the new tensor is not finite and positive at step " +
                                            std::to_string(c->n + 1));
     }
-    // C row index ((a kb + b) kc + c) Dm + mu1, column likewise with primes
-    const uint64_t cs_a = (uint64_t)k[1] * k[2] * Dm, cs_b = (uint64_t)k[2] * Dm, cs_c = Dm;
+    // C row index ((a kb + b) Dm + mu1) kc + c, column likewise with primes
+    const uint64_t cs_a = (uint64_t)k[1] * Dm * k[2], cs_b = (uint64_t)Dm * k[2], cs_m = k[2], cs_c = 1;
     const uint64_t rowst = M;
     int ext[8];
     uint32_t st[8];
     for (int q = 0; q < 4; ++q) {
         ext[2 * q] = ext[2 * q + 1] = Dn[q];
-        if (q == mu) {
-            st[2 * q] = (uint32_t)rowst;
-            st[2 * q + 1] = 1;
-        } else {
-            int i = (q == tv[0]) ? 0 : (q == tv[1] ? 1 : 2);
-            uint64_t s = i == 0 ? cs_a : (i == 1 ? cs_b : cs_c);
-            st[2 * q] = (uint32_t)(s * rowst);
-            st[2 * q + 1] = (uint32_t)s;
-        }
+        uint64_t s;
+        if (q == mu) s = cs_m;
+        else s = (q == tv[0]) ? cs_a : (q == tv[1] ? cs_b : cs_c);
+        st[2 * q] = (uint32_t)(s * rowst);
+        st[2 * q + 1] = (uint32_t)s;
     }
     uint64_t mx = 0;
     PermParams pp = perm_params(8, ext, st, &mx);

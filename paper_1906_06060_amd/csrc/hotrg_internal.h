@@ -48,6 +48,42 @@ struct ModeParams {
     uint32_t u_st[MP_MAXD];
 };
 
+// Vectorised isometry product: each thread owns one `outer` index and writes
+// the J consecutive outputs of the innermost output dimension j:
+//   out[o * J + j] = sum_{i < nsum} U[u(o) + i us + j uj] * in[x(o) + i xs + j xj].
+// Either the isometry (uj != 0, xj == 0: the input run is loaded once) or the
+// input (xj != 0, uj == 0: the isometry column is loaded once) carries j.
+constexpr int VM_MAXJ = 16;
+struct VecModeParams {
+    int nd;  // outer dims
+    int J, nsum;
+    uint32_t outer_total;
+    uint32_t xs, us, xj, uj;
+    FastDiv ext[MP_MAXD];
+    uint32_t in_st[MP_MAXD];
+    uint32_t u_st[MP_MAXD];
+};
+
+// Isometry product with wave-uniform isometry addresses.  A thread owns one
+// index of the `thread` dims (which address the input and the output) and
+// loops over up to two `loop` dims that only address the isometry and the
+// output:
+//   out[o(t) + l1 o1 + l2 o2] = sum_{i < nsum} U[l1 u1 + l2 u2 + i us] * in[x(t) + i xs].
+// The input run (nsum values) is loaded once per thread; every isometry load
+// is the same for all lanes.  With o2 == 1 the l2 outputs of a thread are
+// written as one contiguous run.
+constexpr int XP_MAXD = 8;
+constexpr int XP_MAXS = 16;
+struct ExpandParams {
+    int nd;
+    int L1, L2, nsum;
+    uint32_t threads;
+    uint32_t u1, u2, o1, o2, xs, us;
+    FastDiv ext[XP_MAXD];
+    uint32_t in_st[XP_MAXD];
+    uint32_t out_st[XP_MAXD];
+};
+
 constexpr int PERM_MAXD = 8;
 struct PermParams {
     int nd;
@@ -64,6 +100,12 @@ void launch_mode_product(const ModeParams &p, const double *in, const double *U,
                          hipStream_t s);
 void launch_mode_product_split(const ModeParams &p, const double *in, const double *U,
                                uint16_t *hi, uint16_t *lo, hipStream_t s);
+// out (FP64) or hi/lo (bf16 split) when hi != nullptr
+void launch_mode_product_vec(const VecModeParams &p, const double *in, const double *U, double *out,
+                             uint16_t *hi, uint16_t *lo, hipStream_t s);
+// out (FP64) or hi/lo (bf16 split) when hi != nullptr
+void launch_iso_expand(const ExpandParams &p, const double *in, const double *U, double *out,
+                       uint16_t *hi, uint16_t *lo, hipStream_t s);
 // sum of squares of x[0..n) -> *out (device), deterministic two-pass reduction
 void launch_sumsq(const double *x, size_t n, double *partials, int npartials, double *out,
                   hipStream_t s);

@@ -21,15 +21,24 @@ inline int grid_for(size_t n, int per_block = kThreads, int cap = 65536) {
 // Initial tensors, Eqs. (2.2) and (2.6): entry i of the 2^8 array has leg k
 // index (i >> (7 - k)) & 1; T = sum_s v_s prod_k W[s, i_k], S = sum_s s v_s ...
 // ---------------------------------------------------------------------------
+// W[1][i] = (-1)^i W[0][i] (W[1][0] = W[0][0], W[1][1] = -W[0][1]), so both
+// spin states share one product chain of |W| and differ only by the sign
+// (-1)^{#odd legs}: at h = 0 the Z2-odd entries of T (even of S) cancel
+// exactly, with no contraction of a product into the final sum.
 __global__ void init_site_kernel(double *T, double *S, double w00, double w01, double w10,
                                  double w11, double vu, double vd) {
     int i = threadIdx.x;
-    double pu = vu, pd = vd;
+    double m = 1.0;
+    int odd = 0;
     for (int k = 0; k < 8; ++k) {
         int b = (i >> (7 - k)) & 1;
-        pu *= b ? w01 : w00;
-        pd *= b ? w11 : w10;
+        m *= b ? w01 : w00;
+        odd ^= b;
     }
+    (void)w10;
+    (void)w11;
+    const double pu = vu * m;
+    const double pd = odd ? -(vd * m) : vd * m;
     T[i] = pu + pd;
     S[i] = pu - pd;
 }
@@ -117,6 +126,144 @@ __global__ void __launch_bounds__(kThreads) mode_product_split_kernel(ModeParams
         uint16_t l = bf16_bits((float)(a - bf16_value(h)));
         hi[o] = h;
         lo[o] = l;
+    }
+}
+
+template <bool U_CARRIES_J, bool SPLIT>
+__global__ void __launch_bounds__(kThreads) mode_product_vec_kernel(VecModeParams p, const double *__restrict__ in,
+                                                                    const double *__restrict__ U,
+                                                                    double *__restrict__ out,
+                                                                    uint16_t *__restrict__ hi,
+                                                                    uint16_t *__restrict__ lo) {
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.outer_total; o += gridDim.x * blockDim.x) {
+        uint32_t rem = o, ib = 0, ub = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.ext[k]);
+            uint32_t c = rem - q * p.ext[k].d;
+            ib += c * p.in_st[k];
+            ub += c * p.u_st[k];
+            rem = q;
+        }
+        double v[VM_MAXJ];  // the operand that does not depend on j
+#pragma unroll
+        for (int i = 0; i < VM_MAXJ; ++i)
+            v[i] = i < p.nsum ? (U_CARRIES_J ? in[ib + i * p.xs] : U[ub + i * p.us]) : 0.0;
+        const uint32_t ob = o * (uint32_t)p.J;
+#pragma unroll
+        for (int j = 0; j < VM_MAXJ; ++j) {
+            if (j >= p.J) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < VM_MAXJ; ++i) {
+                if (i >= p.nsum) break;
+                double w = U_CARRIES_J ? U[ub + i * p.us + j * p.uj] : in[ib + i * p.xs + j * p.xj];
+                acc = fma(w, v[i], acc);
+            }
+            if (SPLIT) {
+                uint16_t h = bf16_bits((float)acc);
+                hi[ob + j] = h;
+                lo[ob + j] = bf16_bits((float)(acc - bf16_value(h)));
+            } else {
+                out[ob + j] = acc;
+            }
+        }
+    }
+}
+
+void launch_mode_product_vec(const VecModeParams &p, const double *in, const double *U, double *out, uint16_t *hi,
+                             uint16_t *lo, hipStream_t s) {
+    if (p.outer_total == 0) return;
+    const int g = grid_for(p.outer_total);
+    const bool uj = p.uj != 0;
+    if (hi) {
+        if (uj) mode_product_vec_kernel<true, true><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
+        else mode_product_vec_kernel<false, true><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
+    } else {
+        if (uj) mode_product_vec_kernel<true, false><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
+        else mode_product_vec_kernel<false, false><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
+    }
+}
+
+template <bool SPLIT, bool RUN>
+__global__ void __launch_bounds__(kThreads) iso_expand_kernel(ExpandParams p, const double *__restrict__ in,
+                                                              const double *__restrict__ U,
+                                                              double *__restrict__ out,
+                                                              uint16_t *__restrict__ hi,
+                                                              uint16_t *__restrict__ lo) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < p.threads; t += gridDim.x * blockDim.x) {
+        uint32_t rem = t, ib = 0, ob = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.ext[k]);
+            uint32_t c = rem - q * p.ext[k].d;
+            ib += c * p.in_st[k];
+            ob += c * p.out_st[k];
+            rem = q;
+        }
+        double v[XP_MAXS];
+#pragma unroll
+        for (int i = 0; i < XP_MAXS; ++i) v[i] = i < p.nsum ? in[ib + i * p.xs] : 0.0;
+        for (int l1 = 0; l1 < p.L1; ++l1) {
+            const double *Ul = U + l1 * p.u1;
+            const uint32_t o = ob + l1 * p.o1;
+            if (RUN) {
+                // o2 == 1: a contiguous run of L2 outputs
+                double r[XP_MAXS];
+#pragma unroll
+                for (int l2 = 0; l2 < XP_MAXS; ++l2) {
+                    double acc = 0.0;
+                    if (l2 < p.L2) {
+#pragma unroll
+                        for (int i = 0; i < XP_MAXS; ++i)
+                            if (i < p.nsum) acc = fma(Ul[l2 * p.u2 + i * p.us], v[i], acc);
+                    }
+                    r[l2] = acc;
+                }
+                if (SPLIT) {
+#pragma unroll
+                    for (int l2 = 0; l2 < XP_MAXS; ++l2) {
+                        if (l2 >= p.L2) break;
+                        uint16_t h = bf16_bits((float)r[l2]);
+                        hi[o + l2] = h;
+                        lo[o + l2] = bf16_bits((float)(r[l2] - bf16_value(h)));
+                    }
+                } else {
+#pragma unroll
+                    for (int l2 = 0; l2 < XP_MAXS; ++l2) {
+                        if (l2 >= p.L2) break;
+                        out[o + l2] = r[l2];
+                    }
+                }
+            } else {
+                for (int l2 = 0; l2 < p.L2; ++l2) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < XP_MAXS; ++i)
+                        if (i < p.nsum) acc = fma(Ul[l2 * p.u2 + i * p.us], v[i], acc);
+                    const uint32_t oo = o + l2 * p.o2;
+                    if (SPLIT) {
+                        uint16_t h = bf16_bits((float)acc);
+                        hi[oo] = h;
+                        lo[oo] = bf16_bits((float)(acc - bf16_value(h)));
+                    } else {
+                        out[oo] = acc;
+                    }
+                }
+            }
+        }
+    }
+}
+
+void launch_iso_expand(const ExpandParams &p, const double *in, const double *U, double *out, uint16_t *hi,
+                       uint16_t *lo, hipStream_t s) {
+    if (p.threads == 0) return;
+    const int g = grid_for(p.threads);
+    const bool run = p.o2 == 1 && p.L2 > 1;
+    if (hi) {
+        if (run) iso_expand_kernel<true, true><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
+        else iso_expand_kernel<true, false><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
+    } else {
+        if (run) iso_expand_kernel<false, true><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
+        else iso_expand_kernel<false, false><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
     }
 }
 

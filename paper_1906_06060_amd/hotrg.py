@@ -87,6 +87,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise HotrgUnavailable(f"{path} not built; run python -m paper_1906_06060_amd.build")
+    # torch ships its own HIP runtime; initialise it before the library is
+    # mapped so both resolve to the same runtime (the device lives there)
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     P = C.c_void_p
     dp = C.POINTER(C.c_double)
@@ -127,6 +134,8 @@ def _dptr(a: np.ndarray):
 
 
 def _current_stream():
+    """torch's current stream (initialising torch's ROCm runtime first, which
+    the library relies on to find the device)."""
     try:
         import torch
         if torch.cuda.is_available():
