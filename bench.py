@@ -36,7 +36,21 @@ def parse():
     p.add_argument("--no-impurities", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=12)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain device copy of 2 GiB (for scaling HBM byte counters)")
     return p.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of exactly 2 GiB read + 2 GiB written:
+    the reference for FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}), flush=True)
 
 
 def cpu_baseline(dcut, rows):
@@ -84,6 +98,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if a.copy_calibration:
+        copy_calibration()
+        return
     from paper_1906_06060_amd import hotrg as H
     prec = H.BF16X3 if a.precision == "bf16x3" else H.FP64
     imp = not a.no_impurities

@@ -500,11 +500,13 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     const bool se_pair = imp && c->n == 0;  // Eq. (2.8): S_e . S_e on the first step
     const int nA = imp ? 3 : 1;
     const int nA_shared = se_pair ? 2 : nA;  // operands multiplying B(T)
-    if (M * Ks >= (1ull << 31)) return set_err(HOTRG_ENOMEM, "operand slice exceeds 2^31 elements");
+    if (M * (Ks + 63) >= (1ull << 31)) return set_err(HOTRG_ENOMEM, "operand slice exceeds 2^31 elements");
     if (M * M * 3 > c->cap * 3) return set_err(HOTRG_EINVAL, "new tensor exceeds capacity");
-    const bool mixed = c->cfg.precision == HOTRG_BF16X3 && (c->n + 1) >= c->cfg.mixed_from_step &&
-                       (Ks % 16 == 0);
-    const uint64_t slice = M * Ks;
+    const bool mixed = c->cfg.precision == HOTRG_BF16X3 && (c->n + 1) >= c->cfg.mixed_from_step;
+    // bf16 operand rows are padded with zero columns to a multiple of the
+    // 64 k the kernel stages at a time
+    const uint64_t ld = mixed ? (Ks + 63) / 64 * 64 : Ks;
+    const uint64_t slice = M * ld;
     const int nB = se_pair ? 2 : 1;
     double *Asl = nullptr, *Bsl = nullptr;
     uint16_t *Ah = nullptr, *Al = nullptr, *Bh = nullptr, *Bl = nullptr;
@@ -514,6 +516,8 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
         Al = Ah + slice * nA;
         Bh = Al + slice * nA;
         Bl = Bh + slice * nB;
+        if (ld != Ks)  // padding columns are never written by the products
+            HIP_TRY(c, hipMemsetAsync(Ah, 0, sizeof(uint16_t) * 2 * slice * (nA + nB), c->stream));
     } else {
         TRY(ensure(c, c->f64_slices, sizeof(double) * slice * (nA + nB)));
         Asl = (double *)c->f64_slices.p;
@@ -545,7 +549,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     // K-part strides of an operand row (b1', c1', a2, b2, c2) and row strides
     const uint64_t ks0 = (uint64_t)Dc * Da * Db * Dc, ks1 = (uint64_t)Da * Db * Dc, ks2 = (uint64_t)Db * Dc,
                    ks3 = Dc;
-    const uint64_t rs0 = (uint64_t)kb * Dm * kc * Ks, rs1 = (uint64_t)Dm * kc * Ks, rs2 = (uint64_t)kc * Ks;
+    const uint64_t rs0 = (uint64_t)kb * Dm * kc * ld, rs1 = (uint64_t)Dm * kc * ld, rs2 = (uint64_t)kc * ld;
 
     bool first_slice = true;
     for (int g = 0; g < Dm; ++g) {       // alpha
@@ -588,7 +592,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.tdim(Dc, y2s[4], ks1);
                     x.tdim(Da, y2s[5], ks2);
                     x.tdim(Db, y2s[6], ks3);
-                    x.loops(kc, 1, Ks, Dc, kc, 1);
+                    x.loops(kc, 1, ld, Dc, kc, 1);
                     x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
                     if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
                     if (mixed)
@@ -637,7 +641,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.tdim(Da, z2s[4], ks2);
                     x.tdim(Db, z2s[5], ks3);
                     x.tdim(Dc, z2s[6], 1);
-                    x.loops(kc, 1, Ks, Dc, (uint64_t)Dc * kc, ks1);
+                    x.loops(kc, 1, ld, Dc, (uint64_t)Dc * kc, ks1);
                     x.sum(Dc, z2s[7], kc);
                     if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
                     if (mixed)
@@ -656,7 +660,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                 double *Cp = c->cbuf + (size_t)row0 * M * M;
                 if (mixed)
                     launch_gemm_bf16x3(Ah + slice * row0, Al + slice * row0, Bh + slice * bidx, Bl + slice * bidx, Cp,
-                                       (int)(M * rows), (int)M, (int)Ks, Ks, Ks, M, first_slice ? 0 : 1, c->stream);
+                                       (int)(M * rows), (int)M, (int)ld, ld, ld, M, first_slice ? 0 : 1, c->stream);
                 else
                     launch_gemm_f64(Asl + slice * row0, Bsl + slice * bidx, Cp, (int)(M * rows), (int)M, (int)Ks, Ks,
                                     Ks, M, first_slice ? 0 : 1, c->stream);

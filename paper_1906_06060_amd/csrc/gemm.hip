@@ -7,12 +7,16 @@
 // are plain LDS-staged MFMA tile loops:
 //   * gemm_f64:    v_mfma_f64_16x16x4_f64, 128 x 128 tile, 4 waves of 64 x 64;
 //   * gemm_bf16x3: v_mfma_f32_32x32x16_bf16 on hi/lo splits (3 products),
-//                  256 x 256 tile, 4 waves of 128 x 128, FP32 accumulation
-//                  inside chunks of 8192 k; each chunk is added into the FP64
-//                  output tile (owned by one workgroup, so no atomics).
+//                  256 x 256 tile, 8 waves of 128 x 64 (two per SIMD), 64 k
+//                  per LDS stage, FP32 accumulation inside chunks of 8192 k;
+//                  each chunk is added into the FP64 output tile (owned by
+//                  one workgroup, so no atomics).  A 4-wave 128 x 128 variant
+//                  is kept for comparison.
 // Tiles are ordered so that the blocks an XCD runs together form a compact
 // patch of the output (shared A rows / B columns stay in that XCD's L2).
 #include "hotrg_internal.h"
+
+#include <algorithm>
 
 namespace hotrg {
 
@@ -122,21 +126,24 @@ void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, 
 
 // ---------------------------------------------------------------- bf16x3 ---
 namespace x3 {
-constexpr int BM = 256, BN = 256, BK = 16, PAD = 8, NT = 256;
+constexpr int BM = 256, BN = 256, PAD = 8, NT = 256;
 constexpr int KC = 8192;  // k per FP32 accumulation chunk
-constexpr int LDK = BK + PAD;
-constexpr size_t LDS_OPERANDS = (size_t)(2 * BM + 2 * BN) * LDK * sizeof(uint16_t);
 constexpr size_t LDS_FLUSH = (size_t)4 * 32 * 129 * sizeof(float);
-constexpr size_t LDS_BYTES = LDS_OPERANDS > LDS_FLUSH ? LDS_OPERANDS : LDS_FLUSH;
+template <int BK>
+constexpr size_t lds_bytes() {
+    return std::max((size_t)(2 * BM + 2 * BN) * (BK + PAD) * sizeof(uint16_t), LDS_FLUSH);
+}
 
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
+template <int BK>
 __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restrict__ Ah,
                                                          const uint16_t *__restrict__ Al,
                                                          const uint16_t *__restrict__ Bh,
                                                          const uint16_t *__restrict__ Bl, double *__restrict__ C,
                                                          int M, int N, int K, size_t lda, size_t ldb, size_t ldc,
                                                          int accumulate, int tiles_m, int tiles_n) {
+    constexpr int LDK = BK + PAD;
     extern __shared__ __align__(16) uint16_t smem[];
     uint16_t *sAh = smem;
     uint16_t *sAl = sAh + BM * LDK;
@@ -257,20 +264,157 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     }
     if (first) flush();
 }
+
+// Eight waves (two per SIMD, each 128 x 64) over the same 256 x 256 tile: a
+// wave waiting on memory or a barrier leaves the matrix core to its partner.
+constexpr int NT8 = 512;
+constexpr size_t LDS_FLUSH8 = (size_t)8 * 32 * 65 * sizeof(float);
+template <int BK>
+constexpr size_t lds_bytes8() {
+    return std::max((size_t)(2 * BM + 2 * BN) * (BK + PAD) * sizeof(uint16_t), LDS_FLUSH8);
+}
+
+template <int BK>
+__global__ void __launch_bounds__(NT8) gemm_bf16x3_w8_kernel(const uint16_t *__restrict__ Ah,
+                                                             const uint16_t *__restrict__ Al,
+                                                             const uint16_t *__restrict__ Bh,
+                                                             const uint16_t *__restrict__ Bl,
+                                                             double *__restrict__ C, int M, int N, int K,
+                                                             size_t lda, size_t ldb, size_t ldc, int accumulate,
+                                                             int tiles_m, int tiles_n) {
+    constexpr int LDK = BK + PAD;
+    constexpr int NQ = BK / 16;  // 16-byte pieces per thread, row and operand (two threads per row)
+    extern __shared__ __align__(16) uint16_t smem[];
+    uint16_t *sAh = smem;
+    uint16_t *sAl = sAh + BM * LDK;
+    uint16_t *sBh = sAl + BM * LDK;
+    uint16_t *sBl = sBh + BN * LDK;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 2, wc = wave & 3;  // wave tile: rows wr*128.., cols wc*64..
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    const int lr = tid >> 1, lk = (tid & 1) * (BK / 2);
+    const bool arow = (m0 + lr) < M, brow = (n0 + lr) < N;
+    const uint16_t *pAh = Ah + (size_t)(arow ? m0 + lr : 0) * lda + lk;
+    const uint16_t *pAl = Al + (size_t)(arow ? m0 + lr : 0) * lda + lk;
+    const uint16_t *pBh = Bh + (size_t)(brow ? n0 + lr : 0) * ldb + lk;
+    const uint16_t *pBl = Bl + (size_t)(brow ? n0 + lr : 0) * ldb + lk;
+
+    u4 r[4 * NQ];
+    const u4 zero = {0u, 0u, 0u, 0u};
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            r[q] = arow ? *(const u4 *)(pAh + k0 + 8 * q) : zero;
+            r[NQ + q] = arow ? *(const u4 *)(pAl + k0 + 8 * q) : zero;
+            r[2 * NQ + q] = brow ? *(const u4 *)(pBh + k0 + 8 * q) : zero;
+            r[3 * NQ + q] = brow ? *(const u4 *)(pBl + k0 + 8 * q) : zero;
+        }
+    };
+
+    flt16 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    const int i32 = lane & 31, kh = (lane >> 5) * 8, lq = (lane >> 5) * 4;
+    bool first = !accumulate;
+    float *sC = (float *)smem;
+    constexpr int SROW = 65;
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float *sw = sC + wave * 32 * SROW;
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    sw[((e >> 2) * 8 + lq + (e & 3)) * SROW + j * 32 + i32] = acc[i][j][e];
+                    acc[i][j][e] = 0.0f;
+                }
+            __syncthreads();
+#pragma unroll 2
+            for (int q = 0; q < 32; ++q) {
+                const int idx = tid + NT8 * q;
+                const int w = idx >> 11, rem = idx & 2047;
+                const int rl = rem >> 6, cl = rem & 63;
+                const int row = m0 + (w >> 2) * 128 + i * 32 + rl;
+                const int col = n0 + (w & 3) * 64 + cl;
+                if (row < M && col < N) {
+                    double *c = C + (size_t)row * ldc + col;
+                    double v = (double)sC[w * 32 * SROW + rl * SROW + cl];
+                    *c = first ? v : *c + v;
+                }
+            }
+            __syncthreads();
+        }
+        first = false;
+    };
+
+    gload(0);
+    for (int kc0 = 0; kc0 < K; kc0 += KC) {
+        const int kend = min(K, kc0 + KC);
+        for (int k0 = kc0; k0 < kend; k0 += BK) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                *(u4 *)(sAh + lr * LDK + lk + 8 * q) = r[q];
+                *(u4 *)(sAl + lr * LDK + lk + 8 * q) = r[NQ + q];
+                *(u4 *)(sBh + lr * LDK + lk + 8 * q) = r[2 * NQ + q];
+                *(u4 *)(sBl + lr * LDK + lk + 8 * q) = r[3 * NQ + q];
+            }
+            __syncthreads();
+            if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 16) {
+                bf16x8 bh[2], bl[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int col = wc * 64 + j * 32 + i32;
+                    bh[j] = *(const bf16x8 *)(sBh + col * LDK + ks + kh);
+                    bl[j] = *(const bf16x8 *)(sBl + col * LDK + ks + kh);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = wr * 128 + i * 32 + i32;
+                    const bf16x8 ah = *(const bf16x8 *)(sAh + row * LDK + ks + kh);
+                    const bf16x8 al = *(const bf16x8 *)(sAl + row * LDK + ks + kh);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        flush();  // FP32 chunk of at most KC k into the FP64 tile
+    }
+    if (first) flush();
+}
 }  // namespace x3
+
+constexpr int kBK = 64;  // k per LDS stage of the production (eight-wave) kernel
 
 void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl, double *C,
                         int M, int N, int K, size_t lda, size_t ldb, size_t ldc, int accumulate, hipStream_t s) {
     if (M <= 0 || N <= 0) return;
+    constexpr size_t lds = x3::lds_bytes8<kBK>();
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)x3::gemm_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)x3::LDS_BYTES);
+        (void)hipFuncSetAttribute((const void *)x3::gemm_bf16x3_w8_kernel<kBK>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr_set = true;
     }
     int tm = (M + x3::BM - 1) / x3::BM, tn = (N + x3::BN - 1) / x3::BN;
-    x3::gemm_bf16x3_kernel<<<tm * tn, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, N, K, lda, ldb, ldc,
-                                                                   accumulate, tm, tn);
+    x3::gemm_bf16x3_w8_kernel<kBK><<<tm * tn, x3::NT8, lds, s>>>(Ah, Al, Bh, Bl, C, M, N, K, lda, ldb, ldc,
+                                                                 accumulate, tm, tn);
 }
 
 }  // namespace hotrg
