@@ -23,6 +23,18 @@ sys.path.insert(0, ROOT)
 PEAK_BF16 = 2.5e15     # MI355X dense bf16 MFMA, flop/s
 PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
 
+# HBM bytes per dispatch of the bf16x3 GEMM at this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
+# plain 2 GiB copy); valid only while the kernel source is the one profiled.
+GEMM_TRAFFIC_BYTES = 379817523717
+GEMM_TRAFFIC_SRC_SHA = "aa724c4d34015b6b"
+
+
+def gemm_source_sha():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1906_06060_amd", "csrc", "gemm.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -161,13 +173,15 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "gemm_bf16x3_kernel" if prec == H.BF16X3 else "gemm_f64_kernel",
+            "kernel": "gemm_bf16x3_w8_kernel<64>" if prec == H.BF16X3 else "gemm_f64_kernel",
             "achieved": round(achieved / 1e12, 3),
             "peak": peak / 1e12,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "issued_frac": round(issue * achieved / peak, 4),
-            "traffic": None,
+            "traffic": (GEMM_TRAFFIC_BYTES if (gemm_source_sha() == GEMM_TRAFFIC_SRC_SHA and D == 10 and imp
+                                                and prec == H.BF16X3) else None),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "launches": st["launches"],
             "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 3),
         },
