@@ -45,7 +45,13 @@ def brute_force(beta: float, h: float, L: tuple) -> dict:
     m = float(np.sum(w * confs[:, 0]) / Z)
     pair = index[tuple((1 % L[0]) if k == 0 else 0 for k in range(d))]
     nn = float(np.sum(w * confs[:, 0] * confs[:, pair]) / Z)
-    return dict(lnz_per_site=lnz, m=m, nn=nn, N=N)
+    # per-site derivatives of lnZ / N: d/dbeta = <sum_bonds s s + h sum s> / N,
+    # d/dh = beta <sum s> / N
+    bond_sum = np.sum(confs[:, bi] * confs[:, bj], axis=1)
+    spin_sum = np.sum(confs, axis=1)
+    dbeta = float(np.sum(w * (bond_sum + h * spin_sum)) / Z) / N
+    dh = beta * float(np.sum(w * spin_sum) / Z) / N
+    return dict(lnz_per_site=lnz, m=m, nn=nn, N=N, dlnz_dbeta=dbeta, dlnz_dh=dh)
 
 
 def transfer_1d(beta: float, h: float, N: int) -> float:

@@ -280,11 +280,20 @@ def isometries(T: np.ndarray, mu: int, dcut: int, labels=None, tau: float = TAU_
 # axis's isometry on both T1 legs, contract with T2 over (i2, i2', alpha),
 # then absorb the remaining isometries pairwise.  Peak size D^{4(d-1)-2}.
 # ---------------------------------------------------------------------------
+def _leg_iso(Us: dict, nu: int, side: int) -> np.ndarray:
+    """Isometry of axis nu on the merged backward (side 0) or forward (side 1)
+    legs.  Us[nu] is one matrix used on both legs (the method), or a pair
+    (U_backward, U_forward) -- used only by the tangent, whose product rule
+    differentiates one leg at a time."""
+    u = Us[nu]
+    return u[side] if isinstance(u, tuple) else u
+
+
 def _absorb_remaining(Y, order, t1_shape, t2_shape, Us, transverse, first):
     """Absorb U_nu for transverse[first:] pairwise on the (T1 leg, T2 leg) pairs."""
     for j, nu in enumerate(transverse[first:], start=first):
-        U = Us[nu].reshape(t1_shape[2 * j], t2_shape[2 * j], -1)
         for side in (0, 1):
+            U = _leg_iso(Us, nu, side).reshape(t1_shape[2 * j], t2_shape[2 * j], -1)
             p1 = order.index(("r1", 2 * j + side))
             p2 = order.index(("r2", 2 * j + side))
             Y = np.tensordot(Y, U, axes=([p1, p2], [0, 1]))
@@ -313,9 +322,10 @@ def _step_slice(t1: np.ndarray, t2: np.ndarray, Us: dict, transverse: list, pivo
         order = [("r1", i) for i in range(r)] + [("r2", i) for i in range(r)]
         return _absorb_remaining(Y, order, t1.shape, t2.shape, Us, transverse, 0)
     D1, D2 = t1.shape[0], t2.shape[0]
-    U0 = Us[transverse[0]].reshape(D1, D2, -1)           # [i1, i2, new]
-    X = np.tensordot(t1, U0, axes=([0], [0]))            # [i1', rest1.., alpha, i2, a]
-    X = np.tensordot(X, U0, axes=([0], [0]))             # [rest1.., alpha, i2, a, i2', a']
+    U0b = _leg_iso(Us, transverse[0], 0).reshape(D1, D2, -1)   # [i1, i2, new]
+    U0f = _leg_iso(Us, transverse[0], 1).reshape(D1, D2, -1)
+    X = np.tensordot(t1, U0b, axes=([0], [0]))           # [i1', rest1.., alpha, i2, a]
+    X = np.tensordot(X, U0f, axes=([0], [0]))            # [rest1.., alpha, i2, a, i2', a']
     nr = t1.ndim - 3                                      # legs of rest1
     # contract with t2 over (i2, i2', alpha); t2 legs: [i2, i2', rest2.., alpha]
     Y = np.tensordot(X, t2, axes=([nr + 1, nr + 3, nr], [0, 1, t2.ndim - 1]))
@@ -341,8 +351,7 @@ def coarse_grain(T1: np.ndarray, T2: np.ndarray, Us: dict, mu: int, pivot: bool 
         if nu == mu:
             new_dims += [Dm1, Dm2]
         else:
-            k = Us[nu].shape[1]
-            new_dims += [k, k]
+            new_dims += [_leg_iso(Us, nu, 0).shape[1], _leg_iso(Us, nu, 1).shape[1]]
     out = np.zeros(new_dims)
     # move mu legs of T1/T2 to the front for slicing
     tl = [l for l in range(2 * d) if l not in (2 * mu, 2 * mu + 1)]

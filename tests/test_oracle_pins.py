@@ -260,3 +260,40 @@ def test_sampled_entries_match_full_step(mu):
                 idx[2 * nu], idx[2 * nu + 1] = r[q], c[q]
             idx[2 * mu], idx[2 * mu + 1] = r[-1], c[-1]
             assert got[i, j] == pytest.approx(full[tuple(idx)], rel=1e-12, abs=1e-15)
+
+
+# --- forward-mode tangent (reference for the reverse-mode adjoint) ----------
+@pytest.mark.parametrize("d,L,steps", [(2, (4, 4), 4), (3, (2, 2, 2), 3), (4, (2, 2, 1, 1), 2)])
+@pytest.mark.parametrize("beta,h", [(0.3, 0.1), (0.25, 0.0)])
+def test_tangent_equals_brute_force_derivatives(d, L, steps, beta, h):
+    from oracle import tangent as TG
+    b = X.brute_force(beta, h, L)
+    assert TG.run(beta, h, 256, d, steps, "beta")[-1][2] == pytest.approx(b["dlnz_dbeta"], rel=1e-12)
+    assert TG.run(beta, h, 256, d, steps, "h")[-1][2] == pytest.approx(b["dlnz_dh"], rel=1e-11, abs=1e-15)
+
+
+@pytest.mark.parametrize("wrt", ["beta", "h"])
+def test_tangent_agrees_with_central_differences_on_a_truncated_flow(wrt):
+    # the FD error is O(delta^2): it must shrink ~100x from delta = 1e-4 to 1e-5
+    from oracle import tangent as TG
+    beta, h, D, n = 0.1497, 0.02, 4, 6
+    dl = TG.run(beta, h, D, 4, n, wrt)[-1][2]
+    errs = []
+    for delta in (1e-4, 1e-5):
+        bp, hp = (beta + delta, h) if wrt == "beta" else (beta, h + delta)
+        bm, hm = (beta - delta, h) if wrt == "beta" else (beta, h - delta)
+        fp = H.run(bp, hp, D, 4, n, impurities=False).records[-1].lnz_per_site
+        fm = H.run(bm, hm, D, 4, n, impurities=False).records[-1].lnz_per_site
+        errs.append(abs(dl - (fp - fm) / (2 * delta)) / abs(dl))
+    assert errs[1] < 1e-6
+    assert errs[1] < errs[0] / 20 or errs[1] < 1e-9
+
+
+def test_site_tensor_tangent_matches_differences():
+    from oracle import tangent as TG
+    for wrt in ("beta", "h"):
+        T, dT = TG.site_tensor_tangents(0.2, 0.3, 4, wrt)
+        e = 1e-6
+        Tp, _ = H.site_tensors(0.2 + (e if wrt == "beta" else 0), 0.3 + (e if wrt == "h" else 0), 4)
+        Tm, _ = H.site_tensors(0.2 - (e if wrt == "beta" else 0), 0.3 - (e if wrt == "h" else 0), 4)
+        np.testing.assert_allclose(dT, (Tp - Tm) / (2 * e), rtol=1e-7, atol=1e-9)
