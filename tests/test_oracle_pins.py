@@ -286,7 +286,8 @@ def test_tangent_agrees_with_central_differences_on_a_truncated_flow(wrt):
         fm = H.run(bm, hm, D, 4, n, impurities=False).records[-1].lnz_per_site
         errs.append(abs(dl - (fp - fm) / (2 * delta)) / abs(dl))
     assert errs[1] < 1e-6
-    assert errs[1] < errs[0] / 20 or errs[1] < 1e-9
+    # (at delta = 1e-5 rounding of lnZ, ~1e-16 / delta, starts to show for the small h derivative)
+    assert errs[1] < errs[0] / 10 or errs[1] < 1e-8
 
 
 def test_site_tensor_tangent_matches_differences():
