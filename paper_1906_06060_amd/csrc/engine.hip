@@ -103,6 +103,28 @@ struct hotrg_ctx {
     long long gemm_launches = 0;
     double gemm_flops = 0;
     size_t device_bytes = 0;
+
+    // per-step checkpoints for the reverse pass (keep_checkpoints = 1)
+    struct Checkpoint {
+        int dims[4];
+        int axis;
+        int tv[3];
+        int k[3];
+        int n[3];         // n = D^2 of each transverse axis
+        int side[3];      // environment side the isometry came from
+        bool trunc[3];    // isometry from an eigendecomposition (else constant)
+        double c;         // c_n of the step
+        double *T;        // state before the step
+        double *U[3];     // n x k
+        double *lam[3];   // n (chosen side, descending)
+        double *V[3];     // n x n
+    };
+    std::vector<Checkpoint> ckpts;
+    Checkpoint pending{};
+    bool ckpt_broken = false;
+    double c0 = 1.0;
+    // reverse-pass work buffers
+    DevBuf bw[12];
 };
 
 namespace {
@@ -298,6 +320,52 @@ struct XP {
     }
     const ExpandParams &done() {
         p.threads = (uint32_t)threads;
+        return p;
+    }
+};
+
+// Generic contraction description (see EinsumParams), with host bounds checks.
+struct EP {
+    EinsumParams p{};
+    uint64_t nout = 1, S = 1, mx = 0, my = 0, mz = 0;
+    bool bad = false;
+    void o(int ext, uint64_t sx, uint64_t sy, uint64_t sz) {
+        if (p.ndo >= EIN_MAXO) {
+            bad = true;
+            return;
+        }
+        int k = p.ndo++;
+        p.oext[k] = make_fastdiv((uint32_t)ext);
+        p.ox[k] = (uint32_t)sx;
+        p.oy[k] = (uint32_t)sy;
+        p.oz[k] = (uint32_t)sz;
+        nout *= (uint64_t)ext;
+        mx += (uint64_t)(ext - 1) * sx;
+        my += (uint64_t)(ext - 1) * sy;
+        mz += (uint64_t)(ext - 1) * sz;
+    }
+    void s(int ext, uint64_t sx, uint64_t sy) {
+        if (p.nds >= EIN_MAXS) {
+            bad = true;
+            return;
+        }
+        int k = p.nds++;
+        p.sext[k] = (uint32_t)ext;
+        p.sx[k] = (uint32_t)sx;
+        p.sy[k] = (uint32_t)sy;
+        S *= (uint64_t)ext;
+        mx += (uint64_t)(ext - 1) * sx;
+        my += (uint64_t)(ext - 1) * sy;
+    }
+    bool fits(uint64_t xa, uint64_t ya, uint64_t za) const {
+        return !bad && nout < (1ull << 31) && S < (1ull << 31) && mx < xa && my < ya && mz < za &&
+               mx < (1ull << 32) && my < (1ull << 32) && mz < (1ull << 32);
+    }
+    EinsumParams done(double alpha, int accumulate) {
+        p.nout = (uint32_t)nout;
+        p.S = (uint32_t)S;
+        p.alpha = alpha;
+        p.accumulate = accumulate;
         return p;
     }
 };
@@ -734,6 +802,43 @@ void transverse_of(int mu, int tv[3]) {
         if (q != mu) tv[j++] = q;
 }
 
+// Copy of everything the reverse pass needs from the step about to run: the
+// state T, the isometries, and (for truncated axes) the chosen side's full
+// eigendecomposition.  Isometries given by the caller count as constants.
+int save_checkpoint(hotrg_ctx *c, int axis, const int tv[3], const int k[3], bool given_u) {
+    hotrg_ctx::Checkpoint cp{};
+    for (int q = 0; q < 4; ++q) cp.dims[q] = c->dims[q];
+    cp.axis = axis;
+    const size_t ts = tensor_size(c->dims);
+    TRY(alloc_n(c, &cp.T, ts));
+    HIP_TRY(c, hipMemcpyAsync(cp.T, c->state[0], sizeof(double) * ts, hipMemcpyDeviceToDevice, c->stream));
+    for (int i = 0; i < 3; ++i) {
+        const int q = tv[i];
+        const int nmat = c->dims[q] * c->dims[q];
+        cp.tv[i] = q;
+        cp.k[i] = k[i];
+        cp.n[i] = nmat;
+        cp.trunc[i] = !given_u && c->dec[q].truncated;
+        cp.side[i] = cp.trunc[i] ? c->dec[q].side : 0;
+        TRY(alloc_n(c, &cp.U[i], (size_t)nmat * k[i]));
+        HIP_TRY(c, hipMemcpyAsync(cp.U[i], c->U[i], sizeof(double) * nmat * k[i], hipMemcpyDeviceToDevice,
+                                  c->stream));
+        cp.lam[i] = cp.V[i] = nullptr;
+        if (cp.trunc[i]) {
+            const int side = c->dec[q].side;
+            TRY(alloc_n(c, &cp.lam[i], (size_t)nmat));
+            TRY(alloc_n(c, &cp.V[i], (size_t)nmat * nmat));
+            HIP_TRY(c, hipMemcpyAsync(cp.lam[i], c->lam + (size_t)2 * i * kMaxEnvN + (size_t)side * nmat,
+                                      sizeof(double) * nmat, hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(cp.V[i],
+                                      c->V + (size_t)2 * i * kMaxEnvN * kMaxEnvN + (size_t)side * nmat * nmat,
+                                      sizeof(double) * nmat * nmat, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    c->pending = cp;
+    return HOTRG_OK;
+}
+
 int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost) {
     if (!c) return set_err(HOTRG_EINVAL, "null context");
     if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
@@ -771,8 +876,14 @@ int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost
     } else {
         TRY(isometries(c, c->state[0], lst, ldim, tv, axis, k));
     }
+    if (c->cfg.keep_checkpoints) TRY(save_checkpoint(c, axis, tv, k, Uhost != nullptr));
     TRY(contract(c, axis, tv, k));
-    return finish_step(c, axis, tv, k);
+    TRY(finish_step(c, axis, tv, k));
+    if (c->cfg.keep_checkpoints) {
+        c->pending.c = c->last_cn;
+        c->ckpts.push_back(c->pending);
+    }
+    return HOTRG_OK;
 }
 
 int read_obs(hotrg_ctx *c, double *tr, double *trm, double *tre, std::vector<double> *A) {
@@ -789,6 +900,465 @@ int read_obs(hotrg_ctx *c, double *tr, double *trm, double *tre, std::vector<dou
     *trm = h[1];
     *tre = h[2];
     if (A) A->assign(h.begin() + 3, h.end());
+    return HOTRG_OK;
+}
+
+// ======================================================= reverse pass ====
+// Work buffers of the reverse pass (grown on demand, kept for later calls).
+enum {
+    BW_TBAR0, BW_TBAR1, BW_CBAR, BW_CBART, BW_AT, BW_BT, BW_ABAR, BW_BBAR, BW_Z1, BW_Z2, BW_YB1, BW_YB2
+};
+
+template <typename T>
+int bw_buf(hotrg_ctx *c, int which, size_t count, T **p) {
+    TRY(ensure(c, c->bw[which], sizeof(T) * std::max<size_t>(count, 1)));
+    *p = (T *)c->bw[which].p;
+    return HOTRG_OK;
+}
+
+constexpr size_t kPartialCap = (size_t)1 << 20;  // doubles of split-sum partials
+
+int run_einsum(hotrg_ctx *c, EP &e, const double *X, uint64_t xa, const double *Y, uint64_t ya, double *out,
+               uint64_t za, double alpha, int accumulate, const char *what) {
+    if (!e.fits(xa, ya, za)) return set_err(HOTRG_EINVAL, std::string(what) + ": launch out of bounds");
+    launch_einsum(e.done(alpha, accumulate), X, Y, out, c->gram_part, kPartialCap, c->stream);
+    return check_launch(c, what);
+}
+
+// Tbar_prev (dims of the checkpoint) = adjoint of one step applied to Tbar
+// (dims after the step).  c_n is a constant (reading R5), so
+// C_bar = perm^-1(Tbar) / c_n, then C = sum_s A_s B_s^T gives
+// A_bar_s = C_bar B_s and B_bar_s = C_bar^T A_s, which flow back through the
+// isometry products into T and the isometries; the isometries flow back
+// through the eigendecomposition and the environments into T.
+int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *Tbar, double *Tprev) {
+    const int *D = cp.dims;
+    const int mu = cp.axis;
+    const int *tv = cp.tv;
+    uint64_t cst[8];
+    canon_strides(D, cst);
+    uint64_t lst[8];
+    int ldim[8];
+    for (int i = 0; i < 3; ++i) {
+        lst[2 * i] = cst[2 * tv[i]];
+        lst[2 * i + 1] = cst[2 * tv[i] + 1];
+        ldim[2 * i] = ldim[2 * i + 1] = D[tv[i]];
+    }
+    lst[6] = cst[2 * mu];
+    lst[7] = cst[2 * mu + 1];
+    ldim[6] = ldim[7] = D[mu];
+    const int Da = D[tv[0]], Db = D[tv[1]], Dc = D[tv[2]], Dm = D[mu];
+    const int ka = cp.k[0], kb = cp.k[1], kc = cp.k[2];
+    const uint64_t M = (uint64_t)ka * kb * Dm * kc;  // rows = columns of C
+    const uint64_t Ks = (uint64_t)Db * Dc * Da * Db * Dc;
+    const uint64_t tsize = tensor_size(D);
+    const double *T = cp.T;
+    const double *Ua = cp.U[0], *Ub = cp.U[1], *Uc = cp.U[2];
+    const uint64_t usz[3] = {(uint64_t)Da * Da * ka, (uint64_t)Db * Db * kb, (uint64_t)Dc * Dc * kc};
+    if (M * Ks >= (1ull << 31) || M * M >= (1ull << 31))
+        return set_err(HOTRG_ENOMEM, "reverse pass: operand slice exceeds 2^31 elements");
+
+    double *Cbar, *CbarT, *AT, *BT, *Abar, *Bbar, *Z1, *Z2, *Yb1, *Yb2;
+    TRY(bw_buf(c, BW_CBAR, M * M, &Cbar));
+    TRY(bw_buf(c, BW_CBART, M * M, &CbarT));
+    TRY(bw_buf(c, BW_AT, M * Ks, &AT));
+    TRY(bw_buf(c, BW_BT, M * Ks, &BT));
+    TRY(bw_buf(c, BW_ABAR, M * Ks, &Abar));
+    TRY(bw_buf(c, BW_BBAR, M * Ks, &Bbar));
+    TRY(bw_buf(c, BW_Z1, c->cap, &Z1));
+    TRY(bw_buf(c, BW_Z2, c->cap, &Z2));
+    TRY(bw_buf(c, BW_YB1, c->cap, &Yb1));
+    TRY(bw_buf(c, BW_YB2, c->cap, &Yb2));
+    double *Y1 = c->y1, *Y2 = c->y2;
+    double *Ubar[3];  // in the forward's eigenvector scratch, free during the reverse pass
+    for (int i = 0; i < 3; ++i) Ubar[i] = c->V + (size_t)i * kMaxEnvN * kMaxEnvN;
+    for (int i = 0; i < 3; ++i) launch_zero(Ubar[i], usz[i], c->stream);
+    launch_zero(Tprev, tsize, c->stream);
+
+    // C_bar and its transpose from Tbar (new dims: k on transverse axes, Dm on mu)
+    {
+        int Dn[4];
+        for (int q = 0; q < 4; ++q) Dn[q] = D[q];
+        for (int i = 0; i < 3; ++i) Dn[tv[i]] = cp.k[i];
+        uint64_t ncs[8];
+        canon_strides(Dn, ncs);
+        const int ext[8] = {ka, kb, Dm, kc, ka, kb, Dm, kc};
+        uint32_t st[8] = {(uint32_t)ncs[2 * tv[0]], (uint32_t)ncs[2 * tv[1]], (uint32_t)ncs[2 * mu],
+                          (uint32_t)ncs[2 * tv[2]], (uint32_t)ncs[2 * tv[0] + 1], (uint32_t)ncs[2 * tv[1] + 1],
+                          (uint32_t)ncs[2 * mu + 1], (uint32_t)ncs[2 * tv[2] + 1]};
+        uint64_t mx;
+        PermParams pp = perm_params(8, ext, st, &mx);
+        if (mx >= M * M) return set_err(HOTRG_EINVAL, "C_bar launch out of bounds");
+        launch_permute(pp, Tbar, Cbar, 1.0 / cp.c, c->stream);
+        uint32_t stT[8] = {st[4], st[5], st[6], st[7], st[0], st[1], st[2], st[3]};
+        pp = perm_params(8, ext, stT, &mx);
+        launch_permute(pp, Tbar, CbarT, 1.0 / cp.c, c->stream);
+        TRY(check_launch(c, "C_bar"));
+    }
+
+    const int y1e[7] = {ka, Dm, Db, Dc, Da, Dc, Db};
+    uint64_t y1s[7];
+    row_major_strides(7, y1e, y1s);
+    const int y2e[8] = {ka, kb, Dm, Db, Dc, Da, Db, Dc};
+    uint64_t y2s[8];
+    row_major_strides(8, y2e, y2s);
+    const int z1e[7] = {ka, Dm, Da, Db, Dc, Dc, Db};
+    uint64_t z1s[7];
+    row_major_strides(7, z1e, z1s);
+    const int z2e[8] = {ka, kb, Dm, Db, Da, Db, Dc, Dc};
+    uint64_t z2s[8];
+    row_major_strides(8, z2e, z2s);
+    const uint64_t ks0 = (uint64_t)Dc * Da * Db * Dc, ks1 = (uint64_t)Da * Db * Dc, ks2 = (uint64_t)Db * Dc,
+                   ks3 = Dc;
+    // row-index strides of (a, b, mu1, c) in C / the operands
+    const uint64_t r0 = (uint64_t)kb * Dm * kc, r1 = (uint64_t)Dm * kc, r2 = kc;
+
+    for (int g = 0; g < Dm; ++g) {
+        for (int f = 0; f < Da; ++f) {
+            const uint64_t offA = f * lst[1] + g * lst[7];
+            const uint64_t offB = g * lst[6];
+            // ---- recompute the forward intermediates and the operands, transposed ([K][rows])
+            {
+                XP x;  // P1
+                x.tdim(Dm, lst[6], y1s[1]);
+                x.tdim(Db, lst[3], y1s[2]);
+                x.tdim(Dc, lst[5], y1s[3]);
+                x.tdim(Dc, lst[4], y1s[5]);
+                x.tdim(Db, lst[2], y1s[6]);
+                x.loops(ka, 1, y1s[0], Da, ka, y1s[4]);
+                x.sum(Da, lst[0], (uint64_t)Da * ka);
+                if (!x.fits(tsize - offA, usz[0], c->cap)) return set_err(HOTRG_EINVAL, "bw P1 out of bounds");
+                launch_iso_expand(x.done(), T + offA, Ua, Y1, nullptr, nullptr, c->stream);
+            }
+            {
+                XP x;  // P2
+                x.tdim(ka, y1s[0], y2s[0]);
+                x.tdim(Dm, y1s[1], y2s[2]);
+                x.tdim(Db, y1s[2], y2s[3]);
+                x.tdim(Dc, y1s[3], y2s[4]);
+                x.tdim(Da, y1s[4], y2s[5]);
+                x.tdim(Dc, y1s[5], y2s[7]);
+                x.loops(kb, 1, y2s[1], Db, kb, y2s[6]);
+                x.sum(Db, y1s[6], (uint64_t)Db * kb);
+                if (!x.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "bw P2 out of bounds");
+                launch_iso_expand(x.done(), Y1, Ub, Y2, nullptr, nullptr, c->stream);
+            }
+            {
+                XP x;  // P3 -> A^T [K][M]
+                x.tdim(ka, y2s[0], r0);
+                x.tdim(kb, y2s[1], r1);
+                x.tdim(Dm, y2s[2], r2);
+                x.tdim(Db, y2s[3], ks0 * M);
+                x.tdim(Dc, y2s[4], ks1 * M);
+                x.tdim(Da, y2s[5], ks2 * M);
+                x.tdim(Db, y2s[6], ks3 * M);
+                x.loops(kc, 1, 1, Dc, kc, M);
+                x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
+                if (!x.fits(c->cap, usz[2], M * Ks)) return set_err(HOTRG_EINVAL, "bw P3 out of bounds");
+                launch_iso_expand(x.done(), Y2, Uc, AT, nullptr, nullptr, c->stream);
+            }
+            {
+                XP x;  // Q1
+                x.tdim(Dm, lst[7], z1s[1]);
+                x.tdim(Da, lst[0], z1s[2]);
+                x.tdim(Db, lst[2], z1s[3]);
+                x.tdim(Dc, lst[4], z1s[4]);
+                x.tdim(Dc, lst[5], z1s[5]);
+                x.tdim(Db, lst[3], z1s[6]);
+                x.loops(ka, 1, z1s[0], 1, 0, 0);
+                x.sum(Da, lst[1], ka);
+                if (!x.fits(tsize - offB, usz[0] - (uint64_t)f * Da * ka, c->cap))
+                    return set_err(HOTRG_EINVAL, "bw Q1 out of bounds");
+                launch_iso_expand(x.done(), T + offB, Ua + (size_t)f * Da * ka, Z1, nullptr, nullptr, c->stream);
+            }
+            {
+                XP x;  // Q2
+                x.tdim(ka, z1s[0], z2s[0]);
+                x.tdim(Dm, z1s[1], z2s[2]);
+                x.tdim(Da, z1s[2], z2s[4]);
+                x.tdim(Db, z1s[3], z2s[5]);
+                x.tdim(Dc, z1s[4], z2s[6]);
+                x.tdim(Dc, z1s[5], z2s[7]);
+                x.loops(kb, 1, z2s[1], Db, (uint64_t)Db * kb, z2s[3]);
+                x.sum(Db, z1s[6], kb);
+                if (!x.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "bw Q2 out of bounds");
+                launch_iso_expand(x.done(), Z1, Ub, Z2, nullptr, nullptr, c->stream);
+            }
+            {
+                XP x;  // Q3 -> B^T [K][N]
+                x.tdim(ka, z2s[0], r0);
+                x.tdim(kb, z2s[1], r1);
+                x.tdim(Dm, z2s[2], r2);
+                x.tdim(Db, z2s[3], ks0 * M);
+                x.tdim(Da, z2s[4], ks2 * M);
+                x.tdim(Db, z2s[5], ks3 * M);
+                x.tdim(Dc, z2s[6], M);
+                x.loops(kc, 1, 1, Dc, (uint64_t)Dc * kc, ks1 * M);
+                x.sum(Dc, z2s[7], kc);
+                if (!x.fits(c->cap, usz[2], M * Ks)) return set_err(HOTRG_EINVAL, "bw Q3 out of bounds");
+                launch_iso_expand(x.done(), Z2, Uc, BT, nullptr, nullptr, c->stream);
+            }
+            // ---- A_bar = C_bar B, B_bar = C_bar^T A  (FP64 MFMA)
+            launch_gemm_f64(Cbar, BT, Abar, (int)M, (int)Ks, (int)M, M, M, Ks, 0, c->stream);
+            launch_gemm_f64(CbarT, AT, Bbar, (int)M, (int)Ks, (int)M, M, M, Ks, 0, c->stream);
+            TRY(check_launch(c, "reverse GEMMs"));
+
+            // ---- A side: through P3, P2, P1
+            {   // Yb2[a,b,mu1,b1',c1',a2,b2,c1] = sum_{c,c2} Uc[(c1,c2),c] A_bar[(a,b,mu1,c),(b1',c1',a2,b2,c2)]
+                EP e;
+                e.o(ka, r0 * Ks, 0, y2s[0]);
+                e.o(kb, r1 * Ks, 0, y2s[1]);
+                e.o(Dm, r2 * Ks, 0, y2s[2]);
+                e.o(Db, ks0, 0, y2s[3]);
+                e.o(Dc, ks1, 0, y2s[4]);
+                e.o(Da, ks2, 0, y2s[5]);
+                e.o(Db, ks3, 0, y2s[6]);
+                e.o(Dc, 0, (uint64_t)Dc * kc, y2s[7]);
+                e.s(kc, Ks, 1);
+                e.s(Dc, 1, kc);
+                TRY(run_einsum(c, e, Abar, M * Ks, Uc, usz[2], Yb2, c->cap, 1.0, 0, "bw Y2bar"));
+            }
+            {   // Uc_bar[(c1,c2),c] += sum Y2[.., c1] A_bar[(.., c), (.., c2)]
+                EP e;
+                e.o(Dc, y2s[7], 0, (uint64_t)Dc * kc);
+                e.o(Dc, 0, 1, kc);
+                e.o(kc, 0, Ks, 1);
+                e.s(ka, y2s[0], r0 * Ks);
+                e.s(kb, y2s[1], r1 * Ks);
+                e.s(Dm, y2s[2], r2 * Ks);
+                e.s(Db, y2s[3], ks0);
+                e.s(Dc, y2s[4], ks1);
+                e.s(Da, y2s[5], ks2);
+                e.s(Db, y2s[6], ks3);
+                TRY(run_einsum(c, e, Y2, c->cap, Abar, M * Ks, Ubar[2], usz[2], 1.0, 1, "bw Uc_bar (A)"));
+            }
+            {   // Yb1[a,mu1,b1',c1',a2,c1,b1] = sum_{b,b2} Ub[(b1,b2),b] Yb2[a,b,mu1,b1',c1',a2,b2,c1]
+                EP e;
+                e.o(ka, y2s[0], 0, y1s[0]);
+                e.o(Dm, y2s[2], 0, y1s[1]);
+                e.o(Db, y2s[3], 0, y1s[2]);
+                e.o(Dc, y2s[4], 0, y1s[3]);
+                e.o(Da, y2s[5], 0, y1s[4]);
+                e.o(Dc, y2s[7], 0, y1s[5]);
+                e.o(Db, 0, (uint64_t)Db * kb, y1s[6]);
+                e.s(kb, y2s[1], 1);
+                e.s(Db, y2s[6], kb);
+                TRY(run_einsum(c, e, Yb2, c->cap, Ub, usz[1], Yb1, c->cap, 1.0, 0, "bw Y1bar"));
+            }
+            {   // Ub_bar[(b1,b2),b] += sum Y1[.., b1] Yb2[.., b, .., b2, ..]
+                EP e;
+                e.o(Db, y1s[6], 0, (uint64_t)Db * kb);
+                e.o(Db, 0, y2s[6], kb);
+                e.o(kb, 0, y2s[1], 1);
+                e.s(ka, y1s[0], y2s[0]);
+                e.s(Dm, y1s[1], y2s[2]);
+                e.s(Db, y1s[2], y2s[3]);
+                e.s(Dc, y1s[3], y2s[4]);
+                e.s(Da, y1s[4], y2s[5]);
+                e.s(Dc, y1s[5], y2s[7]);
+                TRY(run_einsum(c, e, Y1, c->cap, Yb2, c->cap, Ubar[1], usz[1], 1.0, 1, "bw Ub_bar (A)"));
+            }
+            {   // Tprev[a1,f,b1,b1',c1,c1',mu1,g] += sum_{a,a2} Ua[(a1,a2),a] Yb1[a,mu1,b1',c1',a2,c1,b1]
+                EP e;
+                e.o(Da, 0, (uint64_t)Da * ka, lst[0]);
+                e.o(Db, y1s[6], 0, lst[2]);
+                e.o(Db, y1s[2], 0, lst[3]);
+                e.o(Dc, y1s[5], 0, lst[4]);
+                e.o(Dc, y1s[3], 0, lst[5]);
+                e.o(Dm, y1s[1], 0, lst[6]);
+                e.s(ka, y1s[0], 1);
+                e.s(Da, y1s[4], ka);
+                TRY(run_einsum(c, e, Yb1, c->cap, Ua, usz[0], Tprev + offA, tsize - offA, 1.0, 1, "bw T1bar"));
+            }
+            {   // Ua_bar[(a1,a2),a] += sum T[a1,f,..,g] Yb1[a,..,a2,..]
+                EP e;
+                e.o(Da, lst[0], 0, (uint64_t)Da * ka);
+                e.o(Da, 0, y1s[4], ka);
+                e.o(ka, 0, y1s[0], 1);
+                e.s(Dm, lst[6], y1s[1]);
+                e.s(Db, lst[3], y1s[2]);
+                e.s(Dc, lst[5], y1s[3]);
+                e.s(Dc, lst[4], y1s[5]);
+                e.s(Db, lst[2], y1s[6]);
+                TRY(run_einsum(c, e, T + offA, tsize - offA, Yb1, c->cap, Ubar[0], usz[0], 1.0, 1, "bw Ua_bar (A)"));
+            }
+            // ---- B side: through Q3, Q2, Q1
+            {   // Zb2[a',b',mu2',b1',a2,b2,c2,c2'] = sum_{c',c1'} Uc[(c1',c2'),c'] B_bar[(a',b',mu2',c'),(b1',c1',a2,b2,c2)]
+                EP e;
+                e.o(ka, r0 * Ks, 0, z2s[0]);
+                e.o(kb, r1 * Ks, 0, z2s[1]);
+                e.o(Dm, r2 * Ks, 0, z2s[2]);
+                e.o(Db, ks0, 0, z2s[3]);
+                e.o(Da, ks2, 0, z2s[4]);
+                e.o(Db, ks3, 0, z2s[5]);
+                e.o(Dc, 1, 0, z2s[6]);
+                e.o(Dc, 0, kc, z2s[7]);
+                e.s(kc, Ks, 1);
+                e.s(Dc, ks1, (uint64_t)Dc * kc);
+                TRY(run_einsum(c, e, Bbar, M * Ks, Uc, usz[2], Yb2, c->cap, 1.0, 0, "bw Z2bar"));
+            }
+            {   // Uc_bar[(c1',c2'),c'] += sum Z2[.., c2'] B_bar[(.., c'), (b1', c1', ..)]
+                EP e;
+                e.o(Dc, 0, ks1, (uint64_t)Dc * kc);
+                e.o(Dc, z2s[7], 0, kc);
+                e.o(kc, 0, Ks, 1);
+                e.s(ka, z2s[0], r0 * Ks);
+                e.s(kb, z2s[1], r1 * Ks);
+                e.s(Dm, z2s[2], r2 * Ks);
+                e.s(Db, z2s[3], ks0);
+                e.s(Da, z2s[4], ks2);
+                e.s(Db, z2s[5], ks3);
+                e.s(Dc, z2s[6], 1);
+                TRY(run_einsum(c, e, Z2, c->cap, Bbar, M * Ks, Ubar[2], usz[2], 1.0, 1, "bw Uc_bar (B)"));
+            }
+            {   // Zb1[a',mu2',a2,b2,c2,c2',b2'] = sum_{b',b1'} Ub[(b1',b2'),b'] Zb2[a',b',mu2',b1',a2,b2,c2,c2']
+                EP e;
+                e.o(ka, z2s[0], 0, z1s[0]);
+                e.o(Dm, z2s[2], 0, z1s[1]);
+                e.o(Da, z2s[4], 0, z1s[2]);
+                e.o(Db, z2s[5], 0, z1s[3]);
+                e.o(Dc, z2s[6], 0, z1s[4]);
+                e.o(Dc, z2s[7], 0, z1s[5]);
+                e.o(Db, 0, kb, z1s[6]);
+                e.s(kb, z2s[1], 1);
+                e.s(Db, z2s[3], (uint64_t)Db * kb);
+                TRY(run_einsum(c, e, Yb2, c->cap, Ub, usz[1], Yb1, c->cap, 1.0, 0, "bw Z1bar"));
+            }
+            {   // Ub_bar[(b1',b2'),b'] += sum Z1[.., b2'] Zb2[.., b', .., b1', ..]
+                EP e;
+                e.o(Db, 0, z2s[3], (uint64_t)Db * kb);
+                e.o(Db, z1s[6], 0, kb);
+                e.o(kb, 0, z2s[1], 1);
+                e.s(ka, z1s[0], z2s[0]);
+                e.s(Dm, z1s[1], z2s[2]);
+                e.s(Da, z1s[2], z2s[4]);
+                e.s(Db, z1s[3], z2s[5]);
+                e.s(Dc, z1s[4], z2s[6]);
+                e.s(Dc, z1s[5], z2s[7]);
+                TRY(run_einsum(c, e, Z1, c->cap, Yb2, c->cap, Ubar[1], usz[1], 1.0, 1, "bw Ub_bar (B)"));
+            }
+            {   // Tprev[a2,a2',b2,b2',c2,c2',g,mu2'] += sum_{a'} Ua[(f,a2'),a'] Zb1[a',mu2',a2,b2,c2,c2',b2']
+                EP e;
+                e.o(Da, z1s[2], 0, lst[0]);
+                e.o(Da, 0, ka, lst[1]);
+                e.o(Db, z1s[3], 0, lst[2]);
+                e.o(Db, z1s[6], 0, lst[3]);
+                e.o(Dc, z1s[4], 0, lst[4]);
+                e.o(Dc, z1s[5], 0, lst[5]);
+                e.o(Dm, z1s[1], 0, lst[7]);
+                e.s(ka, z1s[0], 1);
+                TRY(run_einsum(c, e, Yb1, c->cap, Ua + (size_t)f * Da * ka, usz[0] - (uint64_t)f * Da * ka,
+                               Tprev + offB, tsize - offB, 1.0, 1, "bw T2bar"));
+            }
+            {   // Ua_bar[(f,a2'),a'] += sum T[a2,a2',..,g,mu2'] Zb1[a',mu2',a2,..]
+                EP e;
+                e.o(Da, lst[1], 0, ka);
+                e.o(ka, 0, z1s[0], 1);
+                e.s(Da, lst[0], z1s[2]);
+                e.s(Db, lst[2], z1s[3]);
+                e.s(Db, lst[3], z1s[6]);
+                e.s(Dc, lst[4], z1s[4]);
+                e.s(Dc, lst[5], z1s[5]);
+                e.s(Dm, lst[7], z1s[1]);
+                TRY(run_einsum(c, e, T + offB, tsize - offB, Yb1, c->cap, Ubar[0] + (size_t)f * Da * ka,
+                               usz[0] - (uint64_t)f * Da * ka, 1.0, 1, "bw Ua_bar (B)"));
+            }
+        }
+    }
+
+    // ---- isometries -> environments -> T (truncated axes only)
+    for (int i = 0; i < 3; ++i) {
+        if (!cp.trunc[i]) continue;
+        const int Dn = ldim[2 * i], n = cp.n[i], k = cp.k[i];
+        double *Ebar = c->E;  // scratch: n x n
+        launch_eigh_adjoint(cp.V[i], cp.lam[i], Ubar[i], n, k, Ebar, c->stream);
+        TRY(check_launch(c, "eigh adjoint"));
+        const int leg = 2 * i + cp.side[i];
+        double *G1 = c->G, *G2 = c->G + (size_t)kMaxEnvN * kMaxEnvN;
+        double *G1b = c->E + (size_t)2 * kMaxEnvN * kMaxEnvN, *G2b = c->E + (size_t)3 * kMaxEnvN * kMaxEnvN;
+        TRY(gram(c, T, lst, ldim, leg, 7, G1));
+        TRY(gram(c, T, lst, ldim, leg, 6, G2));
+        const uint64_t R = (uint64_t)Dn * Dm, RR = R * R, nn = (uint64_t)n * n;
+        {   // G1bar[(p,a),(p',a')] = sum_{q,q'} Ebar[(p,q),(p',q')] G2[(q,a),(q',a')]
+            EP e;
+            e.o(Dn, (uint64_t)Dn * n, 0, Dm * R);
+            e.o(Dm, 0, R, R);
+            e.o(Dn, Dn, 0, Dm);
+            e.o(Dm, 0, 1, 1);
+            e.s(Dn, n, Dm * R);
+            e.s(Dn, 1, Dm);
+            TRY(run_einsum(c, e, Ebar, nn, G2, RR, G1b, RR, 1.0, 0, "bw G1bar"));
+        }
+        {   // G2bar[(q,a),(q',a')] = sum_{p,p'} Ebar[(p,q),(p',q')] G1[(p,a),(p',a')]
+            EP e;
+            e.o(Dn, n, 0, Dm * R);
+            e.o(Dm, 0, R, R);
+            e.o(Dn, 1, 0, Dm);
+            e.o(Dm, 0, 1, 1);
+            e.s(Dn, (uint64_t)Dn * n, Dm * R);
+            e.s(Dn, Dn, Dm);
+            TRY(run_einsum(c, e, Ebar, nn, G1, RR, G2b, RR, 1.0, 0, "bw G2bar"));
+        }
+        // X_bar = (G_bar + G_bar^T) X for each Gram, scattered back into Tprev
+        for (int gsel = 0; gsel < 2; ++gsel) {
+            const double *Gb = gsel == 0 ? G1b : G2b;
+            const int la = gsel == 0 ? 7 : 6;
+            for (int tr = 0; tr < 2; ++tr) {
+                EP e;
+                const uint64_t sp = tr ? Dm : Dm * R, sa = tr ? 1 : R;       // strides of (p, a) in G_bar
+                const uint64_t sp2 = tr ? Dm * R : Dm, sa2 = tr ? R : 1;     // strides of (p', a')
+                for (int l = 0; l < 8; ++l) {
+                    if (l == leg) e.o(Dn, sp, 0, lst[l]);
+                    else if (l == la) e.o(Dm, sa, 0, lst[l]);
+                    else e.o(ldim[l], 0, lst[l], lst[l]);
+                }
+                e.s(Dn, sp2, lst[leg]);
+                e.s(Dm, sa2, lst[la]);
+                TRY(run_einsum(c, e, Gb, RR, T, tsize, Tprev, tsize, 1.0, 1, "bw Gram"));
+            }
+        }
+    }
+    return HOTRG_OK;
+}
+
+int backward(hotrg_ctx *c, double *dbeta, double *dh) {
+    if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
+    if (!c->cfg.keep_checkpoints) return set_err(HOTRG_ESTATE, "hotrg_backward needs keep_checkpoints = 1");
+    if (c->ckpt_broken || (int)c->ckpts.size() != c->n)
+        return set_err(HOTRG_ESTATE, "checkpoints do not cover the flow from the initial tensor");
+    if (!(c->beta > 1e-3)) return set_err(HOTRG_EINVAL, "hotrg_backward needs beta > 1e-3");
+    double tr, trm, tre;
+    TRY(read_obs(c, &tr, &trm, &tre, nullptr));
+    if (!(tr > 0) || !std::isfinite(tr)) {
+        c->failed = true;
+        return set_err(HOTRG_ENUMERIC, "Tr T is not finite and positive");
+    }
+    double *Tb, *Tp;
+    TRY(bw_buf(c, BW_TBAR0, c->cap, &Tb));
+    TRY(bw_buf(c, BW_TBAR1, c->cap, &Tp));
+    // seed: d(lnZ/N)/dT^(n) = 2^-n delta_diag / Tr T^(n)
+    uint64_t cst[8];
+    canon_strides(c->dims, cst);
+    uint32_t dst[4];
+    for (int q = 0; q < 4; ++q) dst[q] = (uint32_t)(cst[2 * q] + cst[2 * q + 1]);
+    launch_zero(Tb, tensor_size(c->dims), c->stream);
+    launch_diag_set(Tb, c->dims, dst, std::ldexp(1.0 / tr, -c->n), c->stream);
+    for (int k = c->n - 1; k >= 0; --k) {
+        TRY(backward_step(c, c->ckpts[k], Tb, Tp));
+        std::swap(Tb, Tp);
+    }
+    // d T^(0) / d(beta, h): W[0] = (sqrt cosh b, sqrt sinh b), V = e^{+-b h}
+    const double b = c->beta, h = c->h;
+    const double wc = std::sqrt(std::cosh(b)), ws = std::sqrt(std::sinh(b));
+    const double dwc = std::sinh(b) / (2 * wc), dws = std::cosh(b) / (2 * ws);
+    launch_site_dot(Tb, wc, ws, dwc, dws, b, h, std::exp(b * h), std::exp(-b * h), 1.0 / c->c0, c->scal,
+                    c->stream);
+    TRY(check_launch(c, "site derivative"));
+    double out[2];
+    HIP_TRY(c, hipMemcpyAsync(out, c->scal, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *dbeta = out[0];
+    *dh = out[1];
     return HOTRG_OK;
 }
 
@@ -870,6 +1440,7 @@ int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotr
     launch_permute(pp, c->cbuf + 256, c->state[2], 1.0, c->stream);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(set_err(HOTRG_EDEVICE, "init kernels failed"));
     c->lnz_acc = std::log(c0);
+    c->c0 = c0;
     *out = c;
     return HOTRG_OK;
 }
@@ -937,7 +1508,7 @@ int hotrg_observables(hotrg_ctx *c, hotrg_obs *o) {
 
 int hotrg_backward(hotrg_ctx *c, double *dbeta, double *dh) {
     if (!c || !dbeta || !dh) return set_err(HOTRG_EINVAL, "null argument");
-    return set_err(HOTRG_ESTATE, "backward pass not available in this build");
+    return backward(c, dbeta, dh);
 }
 
 void hotrg_free(hotrg_ctx *c) {
@@ -989,6 +1560,9 @@ int hotrg_set_state(hotrg_ctx *c, const int dims[4], const double *T, const doub
     c->lnz_acc = lnz_acc;
     c->first_axis = n > 0 ? 0 : -1;
     c->last_axis = -1;
+    // steps before this state are unknown: the reverse pass cannot reach beta, h
+    c->ckpts.clear();
+    c->ckpt_broken = true;
     return HOTRG_OK;
 }
 

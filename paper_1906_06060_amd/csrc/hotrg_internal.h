@@ -84,6 +84,21 @@ struct ExpandParams {
     uint32_t out_st[XP_MAXD];
 };
 
+// Generic contraction of two strided views (reverse pass):
+//   out[z(o)] (+)= alpha * sum_s X[x(o) + x(s)] * Y[y(o) + y(s)]
+// o runs over `ndo` output dims (row-major), s over `nds` summed dims.
+constexpr int EIN_MAXO = 10;
+constexpr int EIN_MAXS = 8;
+struct EinsumParams {
+    int ndo, nds;
+    uint32_t nout, S, chunk, nchunks;
+    FastDiv oext[EIN_MAXO];
+    uint32_t ox[EIN_MAXO], oy[EIN_MAXO], oz[EIN_MAXO];
+    uint32_t sext[EIN_MAXS], sx[EIN_MAXS], sy[EIN_MAXS];
+    double alpha;
+    int accumulate;
+};
+
 constexpr int PERM_MAXD = 8;
 struct PermParams {
     int nd;
@@ -123,6 +138,15 @@ void launch_env_combine(const double *G1, const double *G2, int Dp, int Dq, int 
                         hipStream_t s);
 void launch_identity(double *U, int n, hipStream_t s);
 void launch_zero(double *x, size_t n, hipStream_t s);
+
+// reverse pass (kernels_adjoint.hip)
+void launch_einsum(EinsumParams p, const double *X, const double *Y, double *out, double *partial,
+                   size_t partial_cap, hipStream_t s);
+void launch_eigh_adjoint(const double *V, const double *lam, const double *Ubar, int n, int k, double *Ebar,
+                         hipStream_t s);
+void launch_diag_set(double *T, const int D[4], const uint32_t diag_st[4], double value, hipStream_t s);
+void launch_site_dot(const double *Tbar, double wc, double ws, double dwc, double dws, double beta, double h,
+                     double vu, double vd, double inv_c0, double *out, hipStream_t s);
 
 // Jacobi eigensolver: `count` symmetric n x n matrices (n <= 144) at A + i*n*n,
 // eigenvalues (descending) to lam + i*n, eigenvectors as columns of V + i*n*n

@@ -1,0 +1,220 @@
+// Kernels of the reverse-mode pass (adjoint of the coarse-graining chain).
+//
+// * einsum_kernel: a generic two-operand contraction over strided views,
+//     out[z(o)] (+)= alpha * sum_s X[x(o) + x(s)] * Y[y(o) + y(s)],
+//   with the summed multi-index s walked as an odometer (one division per
+//   thread) and optionally split into chunks whose partial sums are added in a
+//   fixed order (deterministic).  Every adjoint of an isometry product, of an
+//   isometry itself, of the environment combination and of the Grams is one
+//   such contraction.
+// * eigh_adjoint_kernel: E_bar = sym(V_perp (F o (V_perp^T U_bar)) U^T) with
+//   F[j, i] = 1 / (lam_i - lam_j) for kept i and discarded j -- the derivative
+//   of the kept eigenvectors restricted to kept x discarded pairs (rotations
+//   inside the kept space are gauge and do not change any trace).
+// * seed and final contraction with dT^(0)/d(beta, h).
+#include "hotrg_internal.h"
+
+namespace hotrg {
+
+namespace {
+constexpr int kT = 256;
+}
+
+__global__ void __launch_bounds__(kT) einsum_kernel(EinsumParams p, const double *__restrict__ X,
+                                                    const double *__restrict__ Y, double *__restrict__ out,
+                                                    double *__restrict__ partial) {
+    const uint32_t ch = blockIdx.y;
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.nout; o += gridDim.x * blockDim.x) {
+        uint32_t rem = o, xb = 0, yb = 0, zb = 0;
+        for (int k = p.ndo - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.oext[k]);
+            uint32_t c = rem - q * p.oext[k].d;
+            xb += c * p.ox[k];
+            yb += c * p.oy[k];
+            zb += c * p.oz[k];
+            rem = q;
+        }
+        const uint32_t s0 = ch * p.chunk;
+        const uint32_t s1 = (p.S - s0 < p.chunk) ? p.S : s0 + p.chunk;
+        double acc = 0.0;
+        if (s0 < p.S) {
+            uint32_t cs[EIN_MAXS];
+            uint32_t xo = 0, yo = 0, r = s0;
+#pragma unroll
+            for (int k = EIN_MAXS - 1; k >= 0; --k) {
+                cs[k] = 0;
+                if (k < p.nds) {
+                    cs[k] = r % p.sext[k];
+                    r /= p.sext[k];
+                    xo += cs[k] * p.sx[k];
+                    yo += cs[k] * p.sy[k];
+                }
+            }
+            for (uint32_t s = s0; s < s1; ++s) {
+                acc = fma(X[xb + xo], Y[yb + yo], acc);
+#pragma unroll
+                for (int k = EIN_MAXS - 1; k >= 0; --k) {
+                    if (k >= p.nds) continue;
+                    cs[k] += 1;
+                    xo += p.sx[k];
+                    yo += p.sy[k];
+                    if (cs[k] < p.sext[k]) break;
+                    cs[k] = 0;
+                    xo -= p.sext[k] * p.sx[k];
+                    yo -= p.sext[k] * p.sy[k];
+                }
+            }
+        }
+        if (p.nchunks == 1) {
+            const double v = p.alpha * acc;
+            out[zb] = p.accumulate ? out[zb] + v : v;
+        } else {
+            partial[(size_t)ch * p.nout + o] = acc;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kT) einsum_reduce_kernel(EinsumParams p, const double *__restrict__ partial,
+                                                           double *__restrict__ out) {
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.nout; o += gridDim.x * blockDim.x) {
+        uint32_t rem = o, zb = 0;
+        for (int k = p.ndo - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.oext[k]);
+            zb += (rem - q * p.oext[k].d) * p.oz[k];
+            rem = q;
+        }
+        double acc = 0.0;
+        for (uint32_t c = 0; c < p.nchunks; ++c) acc += partial[(size_t)c * p.nout + o];
+        const double v = p.alpha * acc;
+        out[zb] = p.accumulate ? out[zb] + v : v;
+    }
+}
+
+void launch_einsum(EinsumParams p, const double *X, const double *Y, double *out, double *partial,
+                   size_t partial_cap, hipStream_t s) {
+    if (p.nout == 0) return;
+    // enough threads to fill the chip: split long sums when there are few outputs
+    uint32_t want = p.nout >= (1u << 18) ? 1u : (uint32_t)(((1u << 18) + p.nout - 1) / p.nout);
+    uint32_t maxc = p.S / 64 > 0 ? p.S / 64 : 1;
+    uint32_t nch = want < maxc ? want : maxc;
+    if (nch > 4096) nch = 4096;
+    while (nch > 1 && (size_t)nch * p.nout > partial_cap) nch /= 2;
+    if (nch < 1) nch = 1;
+    p.nchunks = nch;
+    p.chunk = (p.S + nch - 1) / nch;
+    uint32_t gx = (p.nout + kT - 1) / kT;
+    if (gx > 65535) gx = 65535;
+    einsum_kernel<<<dim3(gx, nch), kT, 0, s>>>(p, X, Y, out, partial);
+    if (nch > 1) einsum_reduce_kernel<<<gx, kT, 0, s>>>(p, partial, out);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the truncated eigenvectors.  V: n x n row-major, column j is the
+// j-th eigenvector (descending lam); U = V[:, :k]; Ubar: n x k row-major.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kT) eigh_adjoint_kernel(const double *__restrict__ V,
+                                                          const double *__restrict__ lam,
+                                                          const double *__restrict__ Ubar, int n, int k,
+                                                          double *__restrict__ Ebar) {
+    __shared__ double Ksh[144 * 12];
+    __shared__ double Zsh[144 * 12];
+    const int m = n - k;
+    for (int idx = threadIdx.x; idx < m * k; idx += blockDim.x) {
+        int j = idx / k, i = idx % k;
+        double w = 0.0;
+        for (int r = 0; r < n; ++r) w = fma(V[r * n + k + j], Ubar[r * k + i], w);
+        Ksh[idx] = w / (lam[i] - lam[k + j]);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * k; idx += blockDim.x) {
+        int r = idx / k, i = idx % k;
+        double z = 0.0;
+        for (int j = 0; j < m; ++j) z = fma(V[r * n + k + j], Ksh[j * k + i], z);
+        Zsh[idx] = z;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        int r = idx / n, c = idx % n;
+        double e1 = 0.0, e2 = 0.0;
+        for (int i = 0; i < k; ++i) {
+            e1 = fma(Zsh[r * k + i], V[c * n + i], e1);
+            e2 = fma(Zsh[c * k + i], V[r * n + i], e2);
+        }
+        Ebar[idx] = 0.5 * (e1 + e2);
+    }
+}
+
+void launch_eigh_adjoint(const double *V, const double *lam, const double *Ubar, int n, int k, double *Ebar,
+                         hipStream_t s) {
+    eigh_adjoint_kernel<<<1, kT, 0, s>>>(V, lam, Ubar, n, k, Ebar);
+}
+
+// ---------------------------------------------------------------------------
+// Seed of the reverse pass: Tbar[x x y y z z t t] = value, zero elsewhere.
+// ---------------------------------------------------------------------------
+__global__ void diag_set_kernel(double *T, int D0, int D1, int D2, int D3, uint32_t s0, uint32_t s1, uint32_t s2,
+                                uint32_t s3, double value) {
+    uint32_t total = (uint32_t)D0 * D1 * D2 * D3;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        uint32_t r = e;
+        uint32_t i3 = r % D3;
+        r /= D3;
+        uint32_t i2 = r % D2;
+        r /= D2;
+        uint32_t i1 = r % D1;
+        uint32_t i0 = r / D1;
+        T[i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3] = value;
+    }
+}
+
+void launch_diag_set(double *T, const int D[4], const uint32_t diag_st[4], double value, hipStream_t s) {
+    diag_set_kernel<<<64, kT, 0, s>>>(T, D[0], D[1], D[2], D[3], diag_st[0], diag_st[1], diag_st[2], diag_st[3],
+                                      value);
+}
+
+// ---------------------------------------------------------------------------
+// <Tbar^(0), dT^(0)/dbeta> and <Tbar^(0), dT^(0)/dh> for the rank-8 tensor of
+// bond dimension 2.  W[0] = (wc, ws), W[1][i] = (-1)^i W[0][i]; dW[0]/dbeta =
+// (dwc, dws) with the same sign rule; v_up = e^{beta h}, v_dn = e^{-beta h}.
+// out[0], out[1] get the two contractions divided by c0.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) site_dot_kernel(const double *__restrict__ Tbar, double wc, double ws,
+                                                       double dwc, double dws, double beta, double h, double vu,
+                                                       double vd, double inv_c0, double *__restrict__ out) {
+    __shared__ double sb[256], sh[256];
+    const int i = threadIdx.x;
+    double m = 1.0, dm = 0.0;
+    int odd = 0;
+    for (int k = 0; k < 8; ++k) {
+        const int b = (i >> (7 - k)) & 1;
+        const double w = b ? ws : wc, dw = b ? dws : dwc;
+        dm = dm * w + m * dw;
+        m *= w;
+        odd ^= b;
+    }
+    const double sg = odd ? -1.0 : 1.0;
+    // T = vu m + vd sg m
+    const double dT_dbeta = h * vu * m + vu * dm - h * vd * sg * m + vd * sg * dm;
+    const double dT_dh = beta * vu * m - beta * vd * sg * m;
+    sb[i] = Tbar[i] * dT_dbeta;
+    sh[i] = Tbar[i] * dT_dh;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (i < w) {
+            sb[i] += sb[i + w];
+            sh[i] += sh[i + w];
+        }
+        __syncthreads();
+    }
+    if (i == 0) {
+        out[0] = sb[0] * inv_c0;
+        out[1] = sh[0] * inv_c0;
+    }
+}
+
+void launch_site_dot(const double *Tbar, double wc, double ws, double dwc, double dws, double beta, double h,
+                     double vu, double vd, double inv_c0, double *out, hipStream_t s) {
+    site_dot_kernel<<<1, 256, 0, s>>>(Tbar, wc, ws, dwc, dws, beta, h, vu, vd, inv_c0, out);
+}
+
+}  // namespace hotrg

@@ -1,0 +1,87 @@
+"""Reverse-mode derivatives of lnZ/N (hotrg_backward) against the oracle's
+forward-mode tangent, brute-force derivatives and central differences."""
+import math
+
+import pytest
+
+from oracle import exact as OX
+from oracle import hotrg as OH
+from oracle import tangent as OT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_1906_06060_amd import hotrg
+    hotrg.load()
+    return hotrg
+
+
+def gpu_grad(H, beta, h, dcut, nsteps, **kw):
+    with H.Context(beta, h, dcut, keep_checkpoints=True, impurities=False, **kw) as ctx:
+        for n in range(nsteps):
+            ctx.step(n % 4)
+        lnz = ctx.lnz()
+        db, dh = ctx.backward()
+    return lnz, db, dh
+
+
+def test_backward_one_step_equals_brute_force(H):
+    beta, h = 0.23, 0.07
+    lnz, db, dh = gpu_grad(H, beta, h, 4, 1)
+    b = OX.brute_force(beta, h, (2, 1, 1, 1))
+    assert lnz == pytest.approx(b["lnz_per_site"], rel=1e-13)
+    assert db == pytest.approx(b["dlnz_dbeta"], rel=1e-12)
+    assert dh == pytest.approx(b["dlnz_dh"], rel=1e-12)
+
+
+def test_backward_at_n0(H):
+    beta, h = 0.3, 0.2
+    with H.Context(beta, h, 4, keep_checkpoints=True, impurities=False) as ctx:
+        db, dh = ctx.backward()
+    b = OX.brute_force(beta, h, (1, 1, 1, 1))
+    assert db == pytest.approx(b["dlnz_dbeta"], rel=1e-13)
+    assert dh == pytest.approx(b["dlnz_dh"], rel=1e-13)
+
+
+@pytest.mark.parametrize("beta,h,dcut,nsteps", [(0.1497, 0.02, 4, 6), (0.14, 0.0, 4, 8), (0.2, 0.05, 3, 6),
+                                               (0.1497, 0.01, 5, 5)])
+def test_backward_matches_oracle_tangent(H, beta, h, dcut, nsteps):
+    lnz, db, dh = gpu_grad(H, beta, h, dcut, nsteps)
+    tb = OT.run(beta, h, dcut, 4, nsteps, "beta")[-1]
+    assert lnz == pytest.approx(tb[1], rel=1e-11)
+    assert db == pytest.approx(tb[2], rel=1e-9)
+    th = OT.run(beta, h, dcut, 4, nsteps, "h")[-1]
+    assert dh == pytest.approx(th[2], rel=1e-8, abs=1e-13)
+
+
+def test_backward_matches_central_differences(H):
+    beta, h, dcut, n, d = 0.1497, 1e-4, 4, 12, 1e-5
+    lnz, db, dh = gpu_grad(H, beta, h, dcut, n)
+
+    def f(b, hh):
+        with H.Context(b, hh, dcut, impurities=False) as ctx:
+            for k in range(n):
+                ctx.step(k % 4)
+            return ctx.lnz()
+    fd_b = (f(beta + d, h) - f(beta - d, h)) / (2 * d)
+    fd_h = (f(beta, h + d) - f(beta, h - d)) / (2 * d)
+    assert db == pytest.approx(fd_b, rel=1e-6)
+    assert dh == pytest.approx(fd_h, rel=1e-4, abs=1e-9)
+
+
+def test_backward_error_paths(H):
+    with H.Context(0.15, 0.0, 4, impurities=False) as ctx:
+        ctx.step(0)
+        with pytest.raises(H.HotrgError) as e:
+            ctx.backward()
+        assert e.value.code == H.ESTATE
+    with H.Context(1e-4, 0.0, 4, impurities=False, keep_checkpoints=True) as ctx:
+        ctx.step(0)
+        with pytest.raises(H.HotrgError) as e:
+            ctx.backward()
+        assert e.value.code == H.EINVAL
