@@ -5,3 +5,10 @@ include/hotrg.h); `paper_1906_06060_amd.hotrg` is its ctypes binding and
 `paper_1906_06060_amd.autograd` wraps ln Z / N as a torch.autograd.Function.
 """
 from . import hotrg  # noqa: F401
+
+
+def __getattr__(name):
+    if name == "autograd":  # imports torch; loaded on first use
+        import importlib
+        return importlib.import_module(".autograd", __name__)
+    raise AttributeError(name)

@@ -85,3 +85,20 @@ def test_backward_error_paths(H):
         with pytest.raises(H.HotrgError) as e:
             ctx.backward()
         assert e.value.code == H.EINVAL
+
+
+def test_autograd_function_gives_energy_and_magnetisation(H):
+    import torch
+    from paper_1906_06060_amd.autograd import lnz_per_site
+    beta0, h0, dcut, n = 0.1497, 0.02, 4, 6
+    beta = torch.tensor(beta0, dtype=torch.float64, requires_grad=True)
+    h = torch.tensor(h0, dtype=torch.float64, requires_grad=True)
+    lnz = lnz_per_site(beta, h, dcut, n)
+    lnz.backward()
+    tb = OT.run(beta0, h0, dcut, 4, n, "beta")[-1]
+    th = OT.run(beta0, h0, dcut, 4, n, "h")[-1]
+    assert lnz.item() == pytest.approx(tb[1], rel=1e-11)
+    energy = -beta.grad.item()
+    magnetisation = h.grad.item() / beta0
+    assert energy == pytest.approx(-tb[2], rel=1e-9)
+    assert magnetisation == pytest.approx(th[2] / beta0, rel=1e-8)
