@@ -48,6 +48,13 @@ def parse():
     p.add_argument("--no-impurities", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=12)
+    p.add_argument("--adjoint", type=int, default=0, metavar="NSTEPS",
+                   help="time an FP64 flow of NSTEPS steps with checkpoints plus hotrg_backward "
+                        "(impurities off; Dcut from --dcut)")
+    p.add_argument("--precision-study", type=int, default=0, metavar="NSTEPS",
+                   help="run bf16x3 and FP64 flows of NSTEPS steps side by side for each --betas "
+                        "and print the per-step differences of lnZ/N, e, m (impurity estimators)")
+    p.add_argument("--betas", type=str, default="0.1490,0.1497,0.1502")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of 2 GiB (for scaling HBM byte counters)")
     return p.parse_args()
@@ -100,6 +107,59 @@ def cpu_baseline(dcut, rows):
     }
 
 
+def precision_study(a):
+    """bf16x3 contraction vs the FP64 path on the same flows (Dcut from --dcut,
+    impurities on): per step the relative difference of lnZ/N and the absolute
+    differences of the impurity energy and magnetisation."""
+    from paper_1906_06060_amd import hotrg as H
+    out = []
+    for beta in [float(b) for b in a.betas.split(",")]:
+        runs = {}
+        for name, prec in (("fp64", H.FP64), ("bf16x3", H.BF16X3)):
+            t0 = time.perf_counter()
+            runs[name] = H.flow(beta, a.h, a.dcut, a.precision_study, precision=prec)
+            runs[name + "_s"] = time.perf_counter() - t0
+        rows = []
+        for f, m in zip(runs["fp64"], runs["bf16x3"]):
+            rows.append({"n": f["n"], "lnz_fp64": f["lnz_per_site"],
+                         "d_lnz_rel": abs(m["lnz_per_site"] - f["lnz_per_site"]) / abs(f["lnz_per_site"]),
+                         "e_fp64": f["e_imp"], "d_e": abs(m["e_imp"] - f["e_imp"]),
+                         "m_fp64": f["m_imp"], "d_m": abs(m["m_imp"] - f["m_imp"]),
+                         "X_fp64": f["X"], "d_X": abs(m["X"] - f["X"])})
+        out.append({"beta": beta, "h": a.h, "dcut": a.dcut, "fp64_s": round(runs["fp64_s"], 2),
+                    "bf16x3_s": round(runs["bf16x3_s"], 2), "steps": rows,
+                    "max_d_lnz_rel": max(r["d_lnz_rel"] for r in rows),
+                    "max_d_e": max(r["d_e"] for r in rows), "max_d_m": max(r["d_m"] for r in rows)})
+        print(json.dumps(out[-1]), flush=True)
+
+
+def adjoint_run(a):
+    """Forward flow with per-step checkpoints, then the reverse pass: the
+    energy and magnetisation of the flow's last step by differentiation."""
+    import torch
+    from paper_1906_06060_amd import hotrg as H
+    ctx = H.Context(a.beta, a.h, a.dcut, precision=H.FP64, impurities=False, keep_checkpoints=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(a.adjoint):
+        ctx.step(n % 4)
+    lnz = ctx.lnz()
+    t1 = time.perf_counter()
+    db, dh = ctx.backward()
+    t2 = time.perf_counter()
+    ob = ctx.observables()
+    ctx.close()
+    print(json.dumps({
+        "metric": "HOTRG forward + reverse-mode adjoint time",
+        "value": round(t2 - t0, 3), "unit": "s", "higher_is_better": False,
+        "config": {"workload": f"4D Ising HOTRG, Dcut={a.dcut}, {a.adjoint} steps, FP64, checkpoints, pure T",
+                   "beta": a.beta, "h": a.h, "dims": list(ob["dims"])},
+        "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+        "lnz_per_site": lnz, "dlnz_dbeta": db, "dlnz_dh": dh,
+        "energy_per_site": -db, "magnetisation": dh / a.beta if a.beta else None,
+    }), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -112,6 +172,12 @@ def main():
         sys.exit(1)
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.adjoint:
+        adjoint_run(a)
+        return
+    if a.precision_study:
+        precision_study(a)
         return
     from paper_1906_06060_amd import hotrg as H
     prec = H.BF16X3 if a.precision == "bf16x3" else H.FP64

@@ -238,3 +238,19 @@ def test_step_errors(H):
         ctx.step(0)
         with pytest.raises(H.HotrgError):
             ctx.isometry(0)
+
+
+# ------------------------------------------------ mixed precision bound ----
+def test_bf16x3_flow_error_bound_against_fp64(H):
+    # Dcut = 8, first 6 steps: steps 1-3 run in FP64 in both (ramp-up), steps
+    # 4-6 contract in bf16x3.  Stated bound (checked): lnZ/N relative <= 1e-6,
+    # impurity energy and magnetisation absolute <= 1e-4.
+    beta, h, dcut, n = 0.1497, 1e-4, 8, 6
+    f = H.flow(beta, h, dcut, n, precision=H.FP64)
+    m = H.flow(beta, h, dcut, n, precision=H.BF16X3)
+    for a, b in zip(f, m):
+        assert b["lnz_per_site"] == pytest.approx(a["lnz_per_site"], rel=1e-6)
+        assert abs(b["e_imp"] - a["e_imp"]) <= 1e-4
+        assert abs(b["m_imp"] - a["m_imp"]) <= 1e-4
+        print(f"n={a['n']} dlnz={abs(b['lnz_per_site'] - a['lnz_per_site']) / a['lnz_per_site']:.2e} "
+              f"de={abs(b['e_imp'] - a['e_imp']):.2e} dm={abs(b['m_imp'] - a['m_imp']):.2e}")
