@@ -239,7 +239,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "gemm_bf16x3_w8_kernel<64>" if prec == H.BF16X3 else "gemm_f64_kernel",
+            "kernel": "gemm_bf16x3_kernel" if prec == H.BF16X3 else "gemm_f64_kernel",
             "achieved": round(achieved / 1e12, 3),
             "peak": peak / 1e12,
             "unit": "TFLOP/s",

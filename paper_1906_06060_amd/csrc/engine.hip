@@ -574,6 +574,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     // bf16 operand rows are padded with zero columns to a multiple of the
     // 64 k the kernel stages at a time
     const uint64_t ld = mixed ? (Ks + 63) / 64 * 64 : Ks;
+    if (mixed && ld >= (1ull << 23)) return set_err(HOTRG_ENOMEM, "bf16 operand row length exceeds 2^23");
     const uint64_t slice = M * ld;
     const int nB = se_pair ? 2 : 1;
     double *Asl = nullptr, *Bsl = nullptr;

@@ -1,17 +1,18 @@
-// Contraction GEMMs of the HOTRG step on the gfx950 matrix cores.
+// Contraction GEMMs of the HOTRG step.
 //
 //   C[M x N] (+)= A[M x K] * B[N x K]^T,   both operands K-contiguous.
 //
 // The O(D^15) contraction of Sec. 2 (cost paragraph) is exactly this
-// product with M = N = D^4 and K = D^7 (taken in K slices), so both kernels
-// are plain LDS-staged MFMA tile loops:
-//   * gemm_f64:    v_mfma_f64_16x16x4_f64, 128 x 128 tile, 4 waves of 64 x 64;
+// product with M = N = D^4 and K = D^7 (taken in K slices):
+//   * gemm_f64:    FP64 on the vector FMA units (on gfx950 they issue at
+//                  about twice the rate of v_mfma_f64_16x16x4 measured in
+//                  register-only loops), 128 x 128 tile, 8 x 8 outputs per
+//                  thread, operands staged k-major in LDS;
 //   * gemm_bf16x3: v_mfma_f32_32x32x16_bf16 on hi/lo splits (3 products),
-//                  256 x 256 tile, 8 waves of 128 x 64 (two per SIMD), 64 k
+//                  256 x 256 tile, 8 waves of 128 x 64 (two per SIMD), 32 k
 //                  per LDS stage, FP32 accumulation inside chunks of 8192 k;
 //                  each chunk is added into the FP64 output tile (owned by
-//                  one workgroup, so no atomics).  A 4-wave 128 x 128 variant
-//                  is kept for comparison.
+//                  one workgroup, so no atomics).
 // Tiles are ordered so that the blocks an XCD runs together form a compact
 // patch of the output (shared A rows / B columns stay in that XCD's L2).
 #include "hotrg_internal.h"
@@ -20,7 +21,6 @@
 
 namespace hotrg {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -44,14 +44,16 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &
 namespace f64 {
 constexpr int BM = 128, BN = 128, BK = 16, PAD = 4, NT = 256;
 
+// Register-blocked DGEMM: a 16 x 16 thread grid, each thread owns rows
+// ty + 16 i and columns tx + 16 j (i, j < 8); operands staged k-major in LDS
+// so that a wave reads 4 broadcast A values and 16 consecutive B values per k.
 __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__ A, const double *__restrict__ B,
-                                                      double *__restrict__ C, int M, int N, int K, size_t lda,
-                                                      size_t ldb, size_t ldc, int accumulate, int tiles_m,
-                                                      int tiles_n) {
+                                                       double *__restrict__ C, int M, int N, int K, size_t lda,
+                                                       size_t ldb, size_t ldc, int accumulate, int tiles_m,
+                                                       int tiles_n) {
     __shared__ double As[BK][BM + PAD];
     __shared__ double Bs[BK][BN + PAD];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
@@ -59,13 +61,11 @@ __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__
     const bool arow = (m0 + lr) < M, brow = (n0 + lr) < N;
     const double *Ap = A + (size_t)(arow ? m0 + lr : 0) * lda;
     const double *Bp = B + (size_t)(brow ? n0 + lr : 0) * ldb;
-
-    dbl4 acc[4][4];
+    double acc[8][8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-
+        for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
     double ra[8], rb[8];
     auto gload = [&](int k0) {
 #pragma unroll
@@ -76,7 +76,6 @@ __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__
         }
     };
     gload(0);
-    const int i16 = lane & 15, k4 = lane >> 4;
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -85,35 +84,33 @@ __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__
         }
         __syncthreads();
         if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll 4
+        for (int kk = 0; kk < BK; ++kk) {
+            double a[8], b[8];
 #pragma unroll
-        for (int kq = 0; kq < BK / 4; ++kq) {
-            double a[4], b[4];
+            for (int i = 0; i < 8; ++i) a[i] = As[kk][ty + 16 * i];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kq * 4 + k4][wr * 64 + i * 16 + i16];
+            for (int j = 0; j < 8; ++j) b[j] = Bs[kk][tx + 16 * j];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kq * 4 + k4][wc * 64 + j * 16 + i16];
+            for (int i = 0; i < 8; ++i)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 8; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
         }
         __syncthreads();
     }
-    // D layout of the 16x16 f64 block: value r of lane l is row l/16 + 4 r, column l%16
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i) {
+        const int row = m0 + ty + 16 * i;
+        if (row >= M) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int row = m0 + wr * 64 + i * 16 + k4 + 4 * r;
-                int col = n0 + wc * 64 + j * 16 + i16;
-                if (row < M && col < N) {
-                    double *c = C + (size_t)row * ldc + col;
-                    *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
-                }
+        for (int j = 0; j < 8; ++j) {
+            const int col = n0 + tx + 16 * j;
+            if (col < N) {
+                double *c = C + (size_t)row * ldc + col;
+                *c = accumulate ? *c + acc[i][j] : acc[i][j];
             }
+        }
+    }
 }
 }  // namespace f64
 
@@ -126,164 +123,22 @@ void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, 
 
 // ---------------------------------------------------------------- bf16x3 ---
 namespace x3 {
-constexpr int BM = 256, BN = 256, PAD = 8, NT = 256;
-constexpr int KC = 8192;  // k per FP32 accumulation chunk
-constexpr size_t LDS_FLUSH = (size_t)4 * 32 * 129 * sizeof(float);
-template <int BK>
-constexpr size_t lds_bytes() {
-    return std::max((size_t)(2 * BM + 2 * BN) * (BK + PAD) * sizeof(uint16_t), LDS_FLUSH);
-}
+constexpr int BM = 256, BN = 256, PAD = 8;
+constexpr int BK = 32;     // k per LDS stage
+constexpr int NT = 512;    // eight waves, two per SIMD, each 128 x 64 of the tile
+constexpr int KC = 8192;   // k per FP32 accumulation chunk
+constexpr int LDK = BK + PAD;
+constexpr size_t LDS_FLUSH = (size_t)8 * 32 * 65 * sizeof(float);
+constexpr size_t LDS_BYTES = std::max((size_t)(2 * BM + 2 * BN) * LDK * sizeof(uint16_t), LDS_FLUSH);
 
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
-template <int BK>
 __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restrict__ Ah,
                                                          const uint16_t *__restrict__ Al,
                                                          const uint16_t *__restrict__ Bh,
                                                          const uint16_t *__restrict__ Bl, double *__restrict__ C,
                                                          int M, int N, int K, size_t lda, size_t ldb, size_t ldc,
                                                          int accumulate, int tiles_m, int tiles_n) {
-    constexpr int LDK = BK + PAD;
-    extern __shared__ __align__(16) uint16_t smem[];
-    uint16_t *sAh = smem;
-    uint16_t *sAl = sAh + BM * LDK;
-    uint16_t *sBh = sAl + BM * LDK;
-    uint16_t *sBl = sBh + BN * LDK;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;  // wave tile: rows wr*128.., cols wc*128..
-    int tm, tn;
-    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
-    const int m0 = tm * BM, n0 = tn * BN;
-
-    // global -> register mapping: thread t owns row t of every operand tile (64 bytes)
-    const int lr = tid;
-    const bool arow = (m0 + lr) < M, brow = (n0 + lr) < N;
-    const uint16_t *pAh = Ah + (size_t)(arow ? m0 + lr : 0) * lda;
-    const uint16_t *pAl = Al + (size_t)(arow ? m0 + lr : 0) * lda;
-    const uint16_t *pBh = Bh + (size_t)(brow ? n0 + lr : 0) * ldb;
-    const uint16_t *pBl = Bl + (size_t)(brow ? n0 + lr : 0) * ldb;
-
-    constexpr int NQ = BK / 8;  // 16-byte pieces per row and operand
-    u4 r[4 * NQ];
-    const u4 zero = {0u, 0u, 0u, 0u};
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            r[q] = arow ? *(const u4 *)(pAh + k0 + 8 * q) : zero;
-            r[NQ + q] = arow ? *(const u4 *)(pAl + k0 + 8 * q) : zero;
-            r[2 * NQ + q] = brow ? *(const u4 *)(pBh + k0 + 8 * q) : zero;
-            r[3 * NQ + q] = brow ? *(const u4 *)(pBl + k0 + 8 * q) : zero;
-        }
-    };
-
-    flt16 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
-
-    // D layout of the 32x32 block: lane l, value e -> row 8*(e/4) + 4*(l/32) + e%4, column l%32
-    const int i32 = lane & 31, kh = (lane >> 5) * 8, lq = (lane >> 5) * 4;
-    bool first = !accumulate;
-    // Add the FP32 partial tile into the FP64 output: in four passes (one per
-    // 32-row block of every wave) the accumulators go through LDS and all 256
-    // threads then update C with coalesced row segments.
-    float *sC = (float *)smem;
-    constexpr int SROW = 129;
-    auto flush = [&]() {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float *sw = sC + wave * 32 * SROW;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    sw[((e >> 2) * 8 + lq + (e & 3)) * SROW + j * 32 + i32] = acc[i][j][e];
-                    acc[i][j][e] = 0.0f;
-                }
-            __syncthreads();
-#pragma unroll 2
-            for (int q = 0; q < 64; ++q) {
-                const int idx = tid + NT * q;
-                const int w = idx >> 12, rem = idx & 4095;
-                const int rl = rem >> 7, cl = rem & 127;
-                const int row = m0 + (w >> 1) * 128 + i * 32 + rl;
-                const int col = n0 + (w & 1) * 128 + cl;
-                if (row < M && col < N) {
-                    double *c = C + (size_t)row * ldc + col;
-                    double v = (double)sC[w * 32 * SROW + rl * SROW + cl];
-                    *c = first ? v : *c + v;
-                }
-            }
-            __syncthreads();
-        }
-        first = false;
-    };
-
-    gload(0);
-    for (int kc0 = 0; kc0 < K; kc0 += KC) {
-        const int kend = min(K, kc0 + KC);
-        for (int k0 = kc0; k0 < kend; k0 += BK) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                *(u4 *)(sAh + lr * LDK + 8 * q) = r[q];
-                *(u4 *)(sAl + lr * LDK + 8 * q) = r[NQ + q];
-                *(u4 *)(sBh + lr * LDK + 8 * q) = r[2 * NQ + q];
-                *(u4 *)(sBl + lr * LDK + 8 * q) = r[3 * NQ + q];
-            }
-            __syncthreads();
-            if (k0 + BK < K) gload(k0 + BK);
-#pragma unroll
-            for (int ks = 0; ks < BK; ks += 16) {
-                bf16x8 bh[4], bl[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int col = wc * 128 + j * 32 + i32;
-                    bh[j] = *(const bf16x8 *)(sBh + col * LDK + ks + kh);
-                    bl[j] = *(const bf16x8 *)(sBl + col * LDK + ks + kh);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int row = wr * 128 + i * 32 + i32;
-                    const bf16x8 ah = *(const bf16x8 *)(sAh + row * LDK + ks + kh);
-                    const bf16x8 al = *(const bf16x8 *)(sAl + row * LDK + ks + kh);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        flush();  // FP32 chunk of at most KC k into the FP64 tile
-    }
-    if (first) flush();
-}
-
-// Eight waves (two per SIMD, each 128 x 64) over the same 256 x 256 tile: a
-// wave waiting on memory or a barrier leaves the matrix core to its partner.
-constexpr int NT8 = 512;
-constexpr size_t LDS_FLUSH8 = (size_t)8 * 32 * 65 * sizeof(float);
-template <int BK>
-constexpr size_t lds_bytes8() {
-    return std::max((size_t)(2 * BM + 2 * BN) * (BK + PAD) * sizeof(uint16_t), LDS_FLUSH8);
-}
-
-template <int BK>
-__global__ void __launch_bounds__(NT8) gemm_bf16x3_w8_kernel(const uint16_t *__restrict__ Ah,
-                                                             const uint16_t *__restrict__ Al,
-                                                             const uint16_t *__restrict__ Bh,
-                                                             const uint16_t *__restrict__ Bl,
-                                                             double *__restrict__ C, int M, int N, int K,
-                                                             size_t lda, size_t ldb, size_t ldc, int accumulate,
-                                                             int tiles_m, int tiles_n) {
-    constexpr int LDK = BK + PAD;
-    constexpr int NQ = BK / 16;  // 16-byte pieces per thread, row and operand (two threads per row)
     extern __shared__ __align__(16) uint16_t smem[];
     uint16_t *sAh = smem;
     uint16_t *sAl = sAh + BM * LDK;
@@ -296,22 +151,43 @@ __global__ void __launch_bounds__(NT8) gemm_bf16x3_w8_kernel(const uint16_t *__r
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
 
-    const int lr = tid >> 1, lk = (tid & 1) * (BK / 2);
-    const bool arow = (m0 + lr) < M, brow = (n0 + lr) < N;
-    const uint16_t *pAh = Ah + (size_t)(arow ? m0 + lr : 0) * lda + lk;
-    const uint16_t *pAl = Al + (size_t)(arow ? m0 + lr : 0) * lda + lk;
-    const uint16_t *pBh = Bh + (size_t)(brow ? n0 + lr : 0) * ldb + lk;
-    const uint16_t *pBl = Bl + (size_t)(brow ? n0 + lr : 0) * ldb + lk;
+    // global -> register mapping: piece p = tid + NT q (q < NQ) of an operand
+    // tile, BK / 8 pieces of 16 bytes per row, is row p / PPR, piece p % PPR,
+    // so one wave instruction reads whole contiguous row segments (a lane
+    // pattern that revisits lines still in flight stalls the vector L1).  The
+    // address is a uniform tile base plus a 32-bit per-lane byte offset (ld is
+    // below 2^23, so 256 ld * 2 < 2^32).
+    constexpr int PPR = BK / 8;
+    constexpr int RPQ = NT / PPR;          // rows covered by one q
+    constexpr int NQ = BM / RPQ;           // 16-byte pieces per thread and operand
+    const int lr = tid / PPR, lk = (tid % PPR) * 8;
+    const char *tAh = (const char *)(Ah + (size_t)m0 * lda), *tAl = (const char *)(Al + (size_t)m0 * lda);
+    const char *tBh = (const char *)(Bh + (size_t)n0 * ldb), *tBl = (const char *)(Bl + (size_t)n0 * ldb);
+    const uint32_t voA = ((uint32_t)lr * (uint32_t)lda + (uint32_t)lk) * 2u;
+    const uint32_t voB = ((uint32_t)lr * (uint32_t)ldb + (uint32_t)lk) * 2u;
+    const int limA = M - m0 - lr, limB = N - n0 - lr;  // piece q exists iff RPQ q < lim
 
     u4 r[4 * NQ];
     const u4 zero = {0u, 0u, 0u, 0u};
     auto gload = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            r[q] = arow ? *(const u4 *)(pAh + k0 + 8 * q) : zero;
-            r[NQ + q] = arow ? *(const u4 *)(pAl + k0 + 8 * q) : zero;
-            r[2 * NQ + q] = brow ? *(const u4 *)(pBh + k0 + 8 * q) : zero;
-            r[3 * NQ + q] = brow ? *(const u4 *)(pBl + k0 + 8 * q) : zero;
+            const size_t ua = ((size_t)(RPQ * q) * lda + k0) * 2, ub = ((size_t)(RPQ * q) * ldb + k0) * 2;
+            const bool va = RPQ * q < limA, vb = RPQ * q < limB;
+            r[q] = va ? *(const u4 *)(tAh + ua + voA) : zero;
+            r[NQ + q] = va ? *(const u4 *)(tAl + ua + voA) : zero;
+            r[2 * NQ + q] = vb ? *(const u4 *)(tBh + ub + voB) : zero;
+            r[3 * NQ + q] = vb ? *(const u4 *)(tBl + ub + voB) : zero;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int so = (lr + RPQ * q) * LDK + lk;
+            *(u4 *)(sAh + so) = r[q];
+            *(u4 *)(sAl + so) = r[NQ + q];
+            *(u4 *)(sBh + so) = r[2 * NQ + q];
+            *(u4 *)(sBl + so) = r[3 * NQ + q];
         }
     };
 
@@ -323,7 +199,38 @@ __global__ void __launch_bounds__(NT8) gemm_bf16x3_w8_kernel(const uint16_t *__r
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
+    // fragments: lane l feeds row (or column) l % 32, k 8 (l / 32) .. + 7 of a
+    // 16-k substep; D layout of the 32x32 block: lane l, value e -> row
+    // 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
     const int i32 = lane & 31, kh = (lane >> 5) * 8, lq = (lane >> 5) * 4;
+    auto compute = [&]() {
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            bf16x8 bh[2], bl[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = wc * 64 + j * 32 + i32;
+                bh[j] = *(const bf16x8 *)(sBh + col * LDK + ks + kh);
+                bl[j] = *(const bf16x8 *)(sBl + col * LDK + ks + kh);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = wr * 128 + i * 32 + i32;
+                const bf16x8 ah = *(const bf16x8 *)(sAh + row * LDK + ks + kh);
+                const bf16x8 al = *(const bf16x8 *)(sAl + row * LDK + ks + kh);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    // Add the FP32 partial tile into the FP64 output: in four passes (one per
+    // 32-row block of every wave) the accumulators go through LDS and all
+    // threads then update C with coalesced row segments.
     bool first = !accumulate;
     float *sC = (float *)smem;
     constexpr int SROW = 65;
@@ -341,7 +248,7 @@ __global__ void __launch_bounds__(NT8) gemm_bf16x3_w8_kernel(const uint16_t *__r
             __syncthreads();
 #pragma unroll 2
             for (int q = 0; q < 32; ++q) {
-                const int idx = tid + NT8 * q;
+                const int idx = tid + NT * q;
                 const int w = idx >> 11, rem = idx & 2047;
                 const int rl = rem >> 6, cl = rem & 63;
                 const int row = m0 + (w >> 2) * 128 + i * 32 + rl;
@@ -357,41 +264,16 @@ __global__ void __launch_bounds__(NT8) gemm_bf16x3_w8_kernel(const uint16_t *__r
         first = false;
     };
 
-    gload(0);
+    // one LDS stage; the next stage's loads are in flight (in registers)
+    // while this one is multiplied
+    if (K > 0) gload(0);
     for (int kc0 = 0; kc0 < K; kc0 += KC) {
         const int kend = min(K, kc0 + KC);
         for (int k0 = kc0; k0 < kend; k0 += BK) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                *(u4 *)(sAh + lr * LDK + lk + 8 * q) = r[q];
-                *(u4 *)(sAl + lr * LDK + lk + 8 * q) = r[NQ + q];
-                *(u4 *)(sBh + lr * LDK + lk + 8 * q) = r[2 * NQ + q];
-                *(u4 *)(sBl + lr * LDK + lk + 8 * q) = r[3 * NQ + q];
-            }
+            store();
             __syncthreads();
             if (k0 + BK < K) gload(k0 + BK);
-#pragma unroll
-            for (int ks = 0; ks < BK; ks += 16) {
-                bf16x8 bh[2], bl[2];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int col = wc * 64 + j * 32 + i32;
-                    bh[j] = *(const bf16x8 *)(sBh + col * LDK + ks + kh);
-                    bl[j] = *(const bf16x8 *)(sBl + col * LDK + ks + kh);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int row = wr * 128 + i * 32 + i32;
-                    const bf16x8 ah = *(const bf16x8 *)(sAh + row * LDK + ks + kh);
-                    const bf16x8 al = *(const bf16x8 *)(sAl + row * LDK + ks + kh);
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-                    }
-                }
-            }
+            compute();
             __syncthreads();
         }
         flush();  // FP32 chunk of at most KC k into the FP64 tile
@@ -400,21 +282,18 @@ __global__ void __launch_bounds__(NT8) gemm_bf16x3_w8_kernel(const uint16_t *__r
 }
 }  // namespace x3
 
-constexpr int kBK = 64;  // k per LDS stage of the production (eight-wave) kernel
-
 void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl, double *C,
                         int M, int N, int K, size_t lda, size_t ldb, size_t ldc, int accumulate, hipStream_t s) {
     if (M <= 0 || N <= 0) return;
-    constexpr size_t lds = x3::lds_bytes8<kBK>();
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)x3::gemm_bf16x3_w8_kernel<kBK>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute((const void *)x3::gemm_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)x3::LDS_BYTES);
         attr_set = true;
     }
     int tm = (M + x3::BM - 1) / x3::BM, tn = (N + x3::BN - 1) / x3::BN;
-    x3::gemm_bf16x3_w8_kernel<kBK><<<tm * tn, x3::NT8, lds, s>>>(Ah, Al, Bh, Bl, C, M, N, K, lda, ldb, ldc,
-                                                                 accumulate, tm, tn);
+    x3::gemm_bf16x3_kernel<<<tm * tn, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, N, K, lda, ldb, ldc,
+                                                                  accumulate, tm, tn);
 }
 
 }  // namespace hotrg

@@ -159,8 +159,9 @@ void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, 
                      size_t ldb, size_t ldc, int accumulate, hipStream_t s);
 // Same product from bf16 hi/lo splits: A ~ Ah + Al, B ~ Bh + Bl; computes
 // Ah Bh^T + Ah Bl^T + Al Bh^T with FP32 MFMA accumulation over chunks of at
-// most 8192 k, summed in FP64.  K must be a multiple of 64 and lda, ldb
-// multiples of 8.
+// most 8192 k, summed in FP64.  K must be a multiple of 64, lda and ldb
+// multiples of 8 and below 2^23 (the kernel forms 32-bit byte offsets of
+// up to 256 rows).
 void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh,
                         const uint16_t *Bl, double *C, int M, int N, int K, size_t lda, size_t ldb,
                         size_t ldc, int accumulate, hipStream_t s);
