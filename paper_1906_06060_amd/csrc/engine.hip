@@ -318,6 +318,12 @@ struct XP {
                threads < (1ull << 31) && max_in < in_avail && max_in < (1ull << 32) && max_u < u_avail &&
                max_out < out_avail && max_out < (1ull << 32);
     }
+    // bf16 outputs go to the packed GEMM layout of a row-major operand with row length ld
+    void packed(uint64_t ld) {
+        p.pack = 1;
+        p.pld = make_fastdiv((uint32_t)ld);
+        p.pkb = (uint32_t)(ld / PACK_K);
+    }
     const ExpandParams &done() {
         p.threads = (uint32_t)threads;
         return p;
@@ -574,19 +580,20 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     // bf16 operand rows are padded with zero columns to a multiple of the
     // 64 k the kernel stages at a time
     const uint64_t ld = mixed ? (Ks + 63) / 64 * 64 : Ks;
-    if (mixed && ld >= (1ull << 23)) return set_err(HOTRG_ENOMEM, "bf16 operand row length exceeds 2^23");
-    const uint64_t slice = M * ld;
+    const uint64_t slice = M * ld;          // row-major operand slice of one tensor
+    const uint64_t pslice = packed_rows(M) * ld;  // the same in the packed bf16 layout
     const int nB = se_pair ? 2 : 1;
     double *Asl = nullptr, *Bsl = nullptr;
     uint16_t *Ah = nullptr, *Al = nullptr, *Bh = nullptr, *Bl = nullptr;
     if (mixed) {
-        TRY(ensure(c, c->x3_slices, sizeof(uint16_t) * 2 * slice * (nA + nB)));
+        TRY(ensure(c, c->x3_slices, sizeof(uint16_t) * 2 * pslice * (nA + nB)));
         Ah = (uint16_t *)c->x3_slices.p;
-        Al = Ah + slice * nA;
-        Bh = Al + slice * nA;
-        Bl = Bh + slice * nB;
-        if (ld != Ks)  // padding columns are never written by the products
-            HIP_TRY(c, hipMemsetAsync(Ah, 0, sizeof(uint16_t) * 2 * slice * (nA + nB), c->stream));
+        Al = Ah + pslice * nA;
+        Bh = Al + pslice * nA;
+        Bl = Bh + pslice * nB;
+        // padding columns are never written by the products and must be zero;
+        // padding rows only reach output rows / columns the GEMM drops
+        if (ld != Ks) HIP_TRY(c, hipMemsetAsync(Ah, 0, sizeof(uint16_t) * 2 * pslice * (nA + nB), c->stream));
     } else {
         TRY(ensure(c, c->f64_slices, sizeof(double) * slice * (nA + nB)));
         Asl = (double *)c->f64_slices.p;
@@ -664,9 +671,11 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.loops(kc, 1, ld, Dc, kc, 1);
                     x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
                     if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
-                    if (mixed)
-                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, Ah + slice * t, Al + slice * t, c->stream);
-                    else
+                    if (mixed) {
+                        x.packed(ld);
+                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, Ah + pslice * t, Al + pslice * t,
+                                          c->stream);
+                    } else
                         launch_iso_expand(x.done(), c->y2, Uc, Asl + slice * t, nullptr, nullptr, c->stream);
                 }
             }
@@ -713,10 +722,11 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.loops(kc, 1, ld, Dc, (uint64_t)Dc * kc, ks1);
                     x.sum(Dc, z2s[7], kc);
                     if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
-                    if (mixed)
-                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, Bh + slice * bidx, Bl + slice * bidx,
+                    if (mixed) {
+                        x.packed(ld);
+                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, Bh + pslice * bidx, Bl + pslice * bidx,
                                           c->stream);
-                    else
+                    } else
                         launch_iso_expand(x.done(), c->y2, Uc, Bsl + slice * bidx, nullptr, nullptr, c->stream);
                 }
             }
@@ -728,8 +738,8 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                 if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
                 double *Cp = c->cbuf + (size_t)row0 * M * M;
                 if (mixed)
-                    launch_gemm_bf16x3(Ah + slice * row0, Al + slice * row0, Bh + slice * bidx, Bl + slice * bidx, Cp,
-                                       (int)(M * rows), (int)M, (int)ld, ld, ld, M, first_slice ? 0 : 1, c->stream);
+                    launch_gemm_bf16x3(Ah + pslice * row0, Al + pslice * row0, Bh + pslice * bidx, Bl + pslice * bidx,
+                                       Cp, (int)M, rows, (int)M, (int)ld, M, first_slice ? 0 : 1, c->stream);
                 else
                     launch_gemm_f64(Asl + slice * row0, Bsl + slice * bidx, Cp, (int)(M * rows), (int)M, (int)Ks, Ks,
                                     Ks, M, first_slice ? 0 : 1, c->stream);

@@ -124,7 +124,7 @@ void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, 
 // ---------------------------------------------------------------- bf16x3 ---
 namespace x3 {
 constexpr int BM = 256, BN = 256, PAD = 8;
-constexpr int BK = 32;     // k per LDS stage
+constexpr int BK = 32;     // k per LDS stage (one packed block)
 constexpr int NT = 512;    // eight waves, two per SIMD, each 128 x 64 of the tile
 constexpr int KC = 8192;   // k per FP32 accumulation chunk
 constexpr int LDK = BK + PAD;
@@ -133,12 +133,17 @@ constexpr size_t LDS_BYTES = std::max((size_t)(2 * BM + 2 * BN) * LDK * sizeof(u
 
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
+// Operands are packed (see hotrg_internal.h): block (row tile, k block) is a
+// contiguous 256 x 32 row-major run, so one stage of one operand is 16 KB of
+// consecutive memory and a wave instruction reads 1 KB of it.  A holds `ntA`
+// tensors of M rows, each padded to Mp = roundup(M, 256); a row tile never
+// straddles two tensors and its rows map to C rows t M + r (r < M).
 __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restrict__ Ah,
                                                          const uint16_t *__restrict__ Al,
                                                          const uint16_t *__restrict__ Bh,
                                                          const uint16_t *__restrict__ Bl, double *__restrict__ C,
-                                                         int M, int N, int K, size_t lda, size_t ldb, size_t ldc,
-                                                         int accumulate, int tiles_m, int tiles_n) {
+                                                         int M, int Mp, int N, int K, size_t ldc, int accumulate,
+                                                         int tiles_m, int tiles_n) {
     extern __shared__ __align__(16) uint16_t smem[];
     uint16_t *sAh = smem;
     uint16_t *sAl = sAh + BM * LDK;
@@ -150,40 +155,33 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
+    const int tens = m0 / Mp, lrow0 = m0 - tens * Mp;  // tensor of this row tile, its first local row
 
-    // global -> register mapping: piece p = tid + NT q (q < NQ) of an operand
-    // tile, BK / 8 pieces of 16 bytes per row, is row p / PPR, piece p % PPR,
-    // so one wave instruction reads whole contiguous row segments (a lane
-    // pattern that revisits lines still in flight stalls the vector L1).  The
-    // address is a uniform tile base plus a 32-bit per-lane byte offset (ld is
-    // below 2^23, so 256 ld * 2 < 2^32).
-    constexpr int PPR = BK / 8;
-    constexpr int RPQ = NT / PPR;          // rows covered by one q
-    constexpr int NQ = BM / RPQ;           // 16-byte pieces per thread and operand
-    const int lr = tid / PPR, lk = (tid % PPR) * 8;
-    const char *tAh = (const char *)(Ah + (size_t)m0 * lda), *tAl = (const char *)(Al + (size_t)m0 * lda);
-    const char *tBh = (const char *)(Bh + (size_t)n0 * ldb), *tBl = (const char *)(Bl + (size_t)n0 * ldb);
-    const uint32_t voA = ((uint32_t)lr * (uint32_t)lda + (uint32_t)lk) * 2u;
-    const uint32_t voB = ((uint32_t)lr * (uint32_t)ldb + (uint32_t)lk) * 2u;
-    const int limA = M - m0 - lr, limB = N - n0 - lr;  // piece q exists iff RPQ q < lim
+    // piece p = tid + NT q of a stage block (16-byte pieces, four per row) is
+    // row p / 4, piece p % 4: element offset 8 p inside the block
+    constexpr int NQ = BM * BK / 8 / NT;  // 2
+    const size_t kb = (size_t)K / BK;     // k blocks per row tile
+    const uint16_t *pAh = Ah + (size_t)tm * kb * (BM * BK) + tid * 8;
+    const uint16_t *pAl = Al + (size_t)tm * kb * (BM * BK) + tid * 8;
+    const uint16_t *pBh = Bh + (size_t)tn * kb * (BN * BK) + tid * 8;
+    const uint16_t *pBl = Bl + (size_t)tn * kb * (BN * BK) + tid * 8;
+    const int lr = tid >> 2, lk = (tid & 3) * 8;
 
     u4 r[4 * NQ];
-    const u4 zero = {0u, 0u, 0u, 0u};
     auto gload = [&](int k0) {
+        const size_t o = (size_t)(k0 / BK) * (BM * BK);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const size_t ua = ((size_t)(RPQ * q) * lda + k0) * 2, ub = ((size_t)(RPQ * q) * ldb + k0) * 2;
-            const bool va = RPQ * q < limA, vb = RPQ * q < limB;
-            r[q] = va ? *(const u4 *)(tAh + ua + voA) : zero;
-            r[NQ + q] = va ? *(const u4 *)(tAl + ua + voA) : zero;
-            r[2 * NQ + q] = vb ? *(const u4 *)(tBh + ub + voB) : zero;
-            r[3 * NQ + q] = vb ? *(const u4 *)(tBl + ub + voB) : zero;
+            r[q] = *(const u4 *)(pAh + o + q * NT * 8);
+            r[NQ + q] = *(const u4 *)(pAl + o + q * NT * 8);
+            r[2 * NQ + q] = *(const u4 *)(pBh + o + q * NT * 8);
+            r[3 * NQ + q] = *(const u4 *)(pBl + o + q * NT * 8);
         }
     };
     auto store = [&]() {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int so = (lr + RPQ * q) * LDK + lk;
+            const int so = (lr + (NT / 4) * q) * LDK + lk;
             *(u4 *)(sAh + so) = r[q];
             *(u4 *)(sAl + so) = r[NQ + q];
             *(u4 *)(sBh + so) = r[2 * NQ + q];
@@ -251,10 +249,10 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
                 const int idx = tid + NT * q;
                 const int w = idx >> 11, rem = idx & 2047;
                 const int rl = rem >> 6, cl = rem & 63;
-                const int row = m0 + (w >> 2) * 128 + i * 32 + rl;
+                const int lrow = lrow0 + (w >> 2) * 128 + i * 32 + rl;
                 const int col = n0 + (w & 3) * 64 + cl;
-                if (row < M && col < N) {
-                    double *c = C + (size_t)row * ldc + col;
+                if (lrow < M && col < N) {
+                    double *c = C + (size_t)(tens * M + lrow) * ldc + col;
                     double v = (double)sC[w * 32 * SROW + rl * SROW + cl];
                     *c = first ? v : *c + v;
                 }
@@ -283,17 +281,18 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
 }  // namespace x3
 
 void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl, double *C,
-                        int M, int N, int K, size_t lda, size_t ldb, size_t ldc, int accumulate, hipStream_t s) {
-    if (M <= 0 || N <= 0) return;
+                        int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s) {
+    if (M <= 0 || N <= 0 || ntA <= 0) return;
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)x3::gemm_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)x3::LDS_BYTES);
         attr_set = true;
     }
-    int tm = (M + x3::BM - 1) / x3::BM, tn = (N + x3::BN - 1) / x3::BN;
-    x3::gemm_bf16x3_kernel<<<tm * tn, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, N, K, lda, ldb, ldc,
-                                                                  accumulate, tm, tn);
+    const int Mp = (M + x3::BM - 1) / x3::BM * x3::BM;
+    const int tm = ntA * (Mp / x3::BM), tn = (N + x3::BN - 1) / x3::BN;
+    x3::gemm_bf16x3_kernel<<<tm * tn, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, Mp, N, K, ldc, accumulate,
+                                                                  tm, tn);
 }
 
 }  // namespace hotrg

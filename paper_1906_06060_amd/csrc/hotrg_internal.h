@@ -74,6 +74,9 @@ struct VecModeParams {
 // written as one contiguous run.
 constexpr int XP_MAXD = 8;
 constexpr int XP_MAXS = 16;
+// With `pack` set (bf16 outputs only) the output offset o = r ld + k of a
+// row-major operand is rewritten to the packed GEMM layout of
+// launch_gemm_bf16x3 (pld = ld, pkb = ld / 32).
 struct ExpandParams {
     int nd;
     int L1, L2, nsum;
@@ -82,6 +85,9 @@ struct ExpandParams {
     FastDiv ext[XP_MAXD];
     uint32_t in_st[XP_MAXD];
     uint32_t out_st[XP_MAXD];
+    int pack;
+    FastDiv pld;
+    uint32_t pkb;
 };
 
 // Generic contraction of two strided views (reverse pass):
@@ -159,11 +165,21 @@ void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, 
                      size_t ldb, size_t ldc, int accumulate, hipStream_t s);
 // Same product from bf16 hi/lo splits: A ~ Ah + Al, B ~ Bh + Bl; computes
 // Ah Bh^T + Ah Bl^T + Al Bh^T with FP32 MFMA accumulation over chunks of at
-// most 8192 k, summed in FP64.  K must be a multiple of 64, lda and ldb
-// multiples of 8 and below 2^23 (the kernel forms 32-bit byte offsets of
-// up to 256 rows).
-void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh,
-                        const uint16_t *Bl, double *C, int M, int N, int K, size_t lda, size_t ldb,
-                        size_t ldc, int accumulate, hipStream_t s);
+// most 8192 k, summed in FP64.  Operands are in the packed layout below; A
+// stacks ntA tensors of M rows each (C rows t M + r), B has N rows; K is a
+// multiple of 64.
+//
+// Packed layout of an operand with R rows and K columns (K a multiple of
+// 32): rows are padded to Rp = roundup(R, 256); element (r, k) sits at
+//   ((r / 256) (K / 32) + k / 32) 8192 + (r % 256) 32 + k % 32,
+// i.e. every 256 x 32 block the GEMM stages at once is one contiguous run.
+constexpr int PACK_ROWS = 256, PACK_K = 32;
+__host__ __device__ inline size_t packed_offset(size_t r, size_t k, size_t K) {
+    return ((r / PACK_ROWS) * (K / PACK_K) + k / PACK_K) * (PACK_ROWS * PACK_K) + (r % PACK_ROWS) * PACK_K +
+           k % PACK_K;
+}
+inline size_t packed_rows(size_t R) { return (R + PACK_ROWS - 1) / PACK_ROWS * PACK_ROWS; }
+void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl,
+                        double *C, int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s);
 
 }  // namespace hotrg

@@ -184,6 +184,15 @@ void launch_mode_product_vec(const VecModeParams &p, const double *in, const dou
     }
 }
 
+// row-major operand offset -> packed GEMM layout (identity when not packed)
+__device__ __forceinline__ size_t split_offset(const ExpandParams &p, uint32_t o) {
+    if (!p.pack) return o;
+    const uint32_t r = fast_div(o, p.pld);
+    const uint32_t k = o - r * p.pld.d;
+    return ((size_t)(r / PACK_ROWS) * p.pkb + k / PACK_K) * (PACK_ROWS * PACK_K) + (r % PACK_ROWS) * PACK_K +
+           k % PACK_K;
+}
+
 template <bool SPLIT, bool RUN>
 __global__ void __launch_bounds__(kThreads) iso_expand_kernel(ExpandParams p, const double *__restrict__ in,
                                                               const double *__restrict__ U,
@@ -223,8 +232,9 @@ __global__ void __launch_bounds__(kThreads) iso_expand_kernel(ExpandParams p, co
                     for (int l2 = 0; l2 < XP_MAXS; ++l2) {
                         if (l2 >= p.L2) break;
                         uint16_t h = bf16_bits((float)r[l2]);
-                        hi[o + l2] = h;
-                        lo[o + l2] = bf16_bits((float)(r[l2] - bf16_value(h)));
+                        const size_t po = split_offset(p, o + l2);
+                        hi[po] = h;
+                        lo[po] = bf16_bits((float)(r[l2] - bf16_value(h)));
                     }
                 } else {
 #pragma unroll
@@ -242,8 +252,9 @@ __global__ void __launch_bounds__(kThreads) iso_expand_kernel(ExpandParams p, co
                     const uint32_t oo = o + l2 * p.o2;
                     if (SPLIT) {
                         uint16_t h = bf16_bits((float)acc);
-                        hi[oo] = h;
-                        lo[oo] = bf16_bits((float)(acc - bf16_value(h)));
+                        const size_t po = split_offset(p, oo);
+                        hi[po] = h;
+                        lo[po] = bf16_bits((float)(acc - bf16_value(h)));
                     } else {
                         out[oo] = acc;
                     }
