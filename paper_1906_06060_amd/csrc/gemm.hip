@@ -10,9 +10,11 @@
 //                  thread, operands staged k-major in LDS;
 //   * gemm_bf16x3: v_mfma_f32_32x32x16_bf16 on hi/lo splits (3 products),
 //                  256 x 256 tile, 8 waves of 128 x 64 (two per SIMD), 32 k
-//                  per LDS stage, FP32 accumulation inside chunks of 8192 k;
-//                  each chunk is added into the FP64 output tile (owned by
-//                  one workgroup, so no atomics).
+//                  per LDS stage loaded directly into a two-slot LDS ring
+//                  (operands in a packed, stage-contiguous layout), FP32
+//                  accumulation inside chunks of 8192 k; each chunk is added
+//                  into the FP64 output tile (owned by one workgroup, so no
+//                  atomics).
 // Tiles are ordered so that the blocks an XCD runs together form a compact
 // patch of the output (shared A rows / B columns stay in that XCD's L2).
 #include "hotrg_internal.h"
@@ -123,21 +125,29 @@ void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, 
 
 // ---------------------------------------------------------------- bf16x3 ---
 namespace x3 {
-constexpr int BM = 256, BN = 256, PAD = 8;
-constexpr int BK = 32;     // k per LDS stage (one packed block)
-constexpr int NT = 512;    // eight waves, two per SIMD, each 128 x 64 of the tile
-constexpr int KC = 8192;   // k per FP32 accumulation chunk
-constexpr int LDK = BK + PAD;
+constexpr int BM = 256, BN = 256;
+constexpr int BK = PACK_K;   // k per LDS stage: one packed block of every operand
+constexpr int NT = 512;      // eight waves, two per SIMD, each 128 x 64 of the tile
+constexpr int KC = 8192;     // k per FP32 accumulation chunk
+constexpr size_t OPB = (size_t)BM * BK * sizeof(uint16_t);  // one operand block: 16 KB
+constexpr size_t STAGE = 4 * OPB;                            // Ah, Al, Bh, Bl: 64 KB
 constexpr size_t LDS_FLUSH = (size_t)8 * 32 * 65 * sizeof(float);
-constexpr size_t LDS_BYTES = std::max((size_t)(2 * BM + 2 * BN) * LDK * sizeof(uint16_t), LDS_FLUSH);
-
-typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+constexpr size_t LDS_BYTES = std::max(2 * STAGE, LDS_FLUSH);  // two-slot ring
+static_assert(KC % BK == 0, "a chunk is whole stages");
 
 // Operands are packed (see hotrg_internal.h): block (row tile, k block) is a
-// contiguous 256 x 32 row-major run, so one stage of one operand is 16 KB of
-// consecutive memory and a wave instruction reads 1 KB of it.  A holds `ntA`
-// tensors of M rows, each padded to Mp = roundup(M, 256); a row tile never
-// straddles two tensors and its rows map to C rows t M + r (r < M).
+// contiguous 256 x 32 run (64-byte rows), so one stage of one operand is 16 KB
+// of consecutive memory.  It goes straight from global memory into LDS
+// (global_load_lds_dwordx4: lane i of a wave writes bytes 16 i .. 16 i + 15 of
+// the wave's 1 KB destination), into a two-slot ring: stage s + 1 is in flight
+// while stage s is multiplied, with no VGPRs spent on staging.  Lane i of a
+// 1 KB chunk (16 rows) fetches piece (i % 4) ^ swz(row) of row i / 4, so LDS
+// position (r, p) holds k piece p ^ swz(r), swz(r) = (r / 4) mod 4: the 16
+// rows that one group of 16 lanes of a fragment read touches fall into 16
+// distinct 16-byte bank groups.
+//
+// A holds `ntA` tensors of M rows, each padded to Mp = roundup(M, 256); a row
+// tile never straddles two tensors and its rows map to C rows t M + r (r < M).
 __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restrict__ Ah,
                                                          const uint16_t *__restrict__ Al,
                                                          const uint16_t *__restrict__ Bh,
@@ -145,11 +155,7 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
                                                          int M, int Mp, int N, int K, size_t ldc, int accumulate,
                                                          int tiles_m, int tiles_n) {
     extern __shared__ __align__(16) uint16_t smem[];
-    uint16_t *sAh = smem;
-    uint16_t *sAl = sAh + BM * LDK;
-    uint16_t *sBh = sAl + BM * LDK;
-    uint16_t *sBl = sBh + BN * LDK;
-
+    char *lds = (char *)smem;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 2, wc = wave & 3;  // wave tile: rows wr*128.., cols wc*64..
     int tm, tn;
@@ -157,35 +163,45 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     const int m0 = tm * BM, n0 = tn * BN;
     const int tens = m0 / Mp, lrow0 = m0 - tens * Mp;  // tensor of this row tile, its first local row
 
-    // piece p = tid + NT q of a stage block (16-byte pieces, four per row) is
-    // row p / 4, piece p % 4: element offset 8 p inside the block
-    constexpr int NQ = BM * BK / 8 / NT;  // 2
-    const size_t kb = (size_t)K / BK;     // k blocks per row tile
-    const uint16_t *pAh = Ah + (size_t)tm * kb * (BM * BK) + tid * 8;
-    const uint16_t *pAl = Al + (size_t)tm * kb * (BM * BK) + tid * 8;
-    const uint16_t *pBh = Bh + (size_t)tn * kb * (BN * BK) + tid * 8;
-    const uint16_t *pBl = Bl + (size_t)tn * kb * (BN * BK) + tid * 8;
-    const int lr = tid >> 2, lk = (tid & 3) * 8;
-
-    u4 r[4 * NQ];
-    auto gload = [&](int k0) {
-        const size_t o = (size_t)(k0 / BK) * (BM * BK);
+    // loads: wave w brings half w % 2 (128 rows, 8 KB) of operand w / 2
+    const size_t kb = (size_t)K / BK;  // packed k blocks per row tile
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int op = wv >> 1, half = wv & 1;
+    const uint16_t *obase = op == 0 ? Ah : (op == 1 ? Al : (op == 2 ? Bh : Bl));
+    const char *src0 = (const char *)(obase + (size_t)(op < 2 ? tm : tn) * kb * (BM * BK)) + half * (OPB / 2);
+    const uint32_t lsrc = (uint32_t)((lane >> 2) * (BK * 2) + (((lane & 3) ^ ((lane >> 4) & 3)) * 16));
+    const uint32_t ldst = (uint32_t)(op * OPB + half * (OPB / 2));
+    auto issue = [&](size_t blk, int slot) {
+        const char *src = src0 + blk * OPB;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            r[q] = *(const u4 *)(pAh + o + q * NT * 8);
-            r[NQ + q] = *(const u4 *)(pAl + o + q * NT * 8);
-            r[2 * NQ + q] = *(const u4 *)(pBh + o + q * NT * 8);
-            r[3 * NQ + q] = *(const u4 *)(pBl + o + q * NT * 8);
-        }
+        for (int j = 0; j < 8; ++j)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void *)(src + j * 1024 + lsrc),
+                (__attribute__((address_space(3))) void *)(lds + slot * STAGE + ldst + j * 1024), 16, 0, 0);
     };
-    auto store = [&]() {
+
+    // fragments: lane l feeds row (or column) l % 32, k 8 (l / 32) .. + 7 of a
+    // 16-k substep; the swizzle of rows r + 32 i equals that of r, and substep
+    // 1 (pieces 2, 3) is position ^ 2, i.e. byte offset ^ 32
+    const int i32 = lane & 31, lq = (lane >> 5) * 4;
+    const uint32_t sw = (uint32_t)(((lane >> 5) ^ ((i32 >> 2) & 3)) * 16);
+    const uint32_t offA = (uint32_t)(wr * 128 + i32) * (BK * 2) + sw;
+    const uint32_t offB = (uint32_t)(2 * OPB) + (uint32_t)(wc * 64 + i32) * (BK * 2) + sw;
+    struct Frags {
+        bf16x8 ah[4], al[4], bh[2], bl[2];
+    };
+    auto read = [&](Frags &f, int slot, int sub) {
+        const char *b = lds + slot * STAGE;
+        const uint32_t x = sub ? 32u : 0u;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int so = (lr + (NT / 4) * q) * LDK + lk;
-            *(u4 *)(sAh + so) = r[q];
-            *(u4 *)(sAl + so) = r[NQ + q];
-            *(u4 *)(sBh + so) = r[2 * NQ + q];
-            *(u4 *)(sBl + so) = r[3 * NQ + q];
+        for (int j = 0; j < 2; ++j) {
+            f.bh[j] = *(const bf16x8 *)(b + ((offB ^ x) + j * 32 * (BK * 2)));
+            f.bl[j] = *(const bf16x8 *)(b + ((offB ^ x) + j * 32 * (BK * 2) + OPB));
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f.ah[i] = *(const bf16x8 *)(b + ((offA ^ x) + i * 32 * (BK * 2)));
+            f.al[i] = *(const bf16x8 *)(b + ((offA ^ x) + i * 32 * (BK * 2) + OPB));
         }
     };
 
@@ -196,34 +212,16 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
-
-    // fragments: lane l feeds row (or column) l % 32, k 8 (l / 32) .. + 7 of a
-    // 16-k substep; D layout of the 32x32 block: lane l, value e -> row
-    // 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
-    const int i32 = lane & 31, kh = (lane >> 5) * 8, lq = (lane >> 5) * 4;
-    auto compute = [&]() {
+    // D layout of the 32x32 block: lane l, value e -> row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
+    auto mma = [&](const Frags &f) {
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 16) {
-            bf16x8 bh[2], bl[2];
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const int col = wc * 64 + j * 32 + i32;
-                bh[j] = *(const bf16x8 *)(sBh + col * LDK + ks + kh);
-                bl[j] = *(const bf16x8 *)(sBl + col * LDK + ks + kh);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[i], f.bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[i], f.bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[i], f.bh[j], acc[i][j], 0, 0, 0);
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = wr * 128 + i * 32 + i32;
-                const bf16x8 ah = *(const bf16x8 *)(sAh + row * LDK + ks + kh);
-                const bf16x8 al = *(const bf16x8 *)(sAl + row * LDK + ks + kh);
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-                }
-            }
-        }
     };
 
     // Add the FP32 partial tile into the FP64 output: in four passes (one per
@@ -235,12 +233,12 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     auto flush = [&]() {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float *sw = sC + wave * 32 * SROW;
+            float *sw_ = sC + wave * 32 * SROW;
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
-                    sw[((e >> 2) * 8 + lq + (e & 3)) * SROW + j * 32 + i32] = acc[i][j][e];
+                    sw_[((e >> 2) * 8 + lq + (e & 3)) * SROW + j * 32 + i32] = acc[i][j][e];
                     acc[i][j][e] = 0.0f;
                 }
             __syncthreads();
@@ -262,19 +260,31 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
         first = false;
     };
 
-    // one LDS stage; the next stage's loads are in flight (in registers)
-    // while this one is multiplied
-    if (K > 0) gload(0);
+    // Per stage: the second substep's fragments are read while the first is on
+    // the matrix core; one barrier per stage, between the substeps, after which
+    // the next stage has landed for every wave and the slot just read may be
+    // refilled; the first fragments of the next stage are then read while the
+    // second substep runs.
     for (int kc0 = 0; kc0 < K; kc0 += KC) {
-        const int kend = min(K, kc0 + KC);
-        for (int k0 = kc0; k0 < kend; k0 += BK) {
-            store();
+        const int nst = (min(K, kc0 + KC) - kc0) / BK;
+        const size_t b0 = (size_t)kc0 / BK;
+        issue(b0, 0);
+        __syncthreads();  // (waits for this wave's loads) stage 0 landed everywhere
+        if (nst > 1) issue(b0 + 1, 1);
+        Frags f0, f1;
+        read(f0, 0, 0);
+        for (int st = 0; st < nst; ++st) {
+            const int slot = st & 1;
+            read(f1, slot, 1);
+            mma(f0);
+            __builtin_amdgcn_s_waitcnt(0);  // own loads of stage st + 1, own reads of this slot
             __syncthreads();
-            if (k0 + BK < K) gload(k0 + BK);
-            compute();
-            __syncthreads();
+            if (st + 2 < nst) issue(b0 + st + 2, slot);
+            if (st + 1 < nst) read(f0, slot ^ 1, 0);
+            mma(f1);
         }
-        flush();  // FP32 chunk of at most KC k into the FP64 tile
+        __syncthreads();  // ring reads done before the flush reuses the LDS
+        flush();          // FP32 chunk of at most KC k into the FP64 tile
     }
     if (first) flush();
 }
