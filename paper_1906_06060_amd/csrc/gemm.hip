@@ -264,27 +264,47 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     // the matrix core; one barrier per stage, between the substeps, after which
     // the next stage has landed for every wave and the slot just read may be
     // refilled; the first fragments of the next stage are then read while the
-    // second substep runs.
+    // second substep runs.  The loop body has no branches (past the end of a
+    // chunk the refill reloads a valid block and the fragments read are not
+    // used), so the scheduling groups below can place one LDS read (and, in
+    // the second substep, one global load) between every two MFMAs.
     for (int kc0 = 0; kc0 < K; kc0 += KC) {
         const int nst = (min(K, kc0 + KC) - kc0) / BK;
-        const size_t b0 = (size_t)kc0 / BK;
+        const size_t b0 = (size_t)kc0 / BK, blast = kb - 1;
         issue(b0, 0);
         __syncthreads();  // (waits for this wave's loads) stage 0 landed everywhere
-        if (nst > 1) issue(b0 + 1, 1);
+        issue(min(b0 + 1, blast), 1);
         Frags f0, f1;
         read(f0, 0, 0);
         for (int st = 0; st < nst; ++st) {
             const int slot = st & 1;
             read(f1, slot, 1);
             mma(f0);
+#pragma unroll
+            for (int g = 0; g < 12; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMAs
+            }
             __builtin_amdgcn_s_waitcnt(0);  // own loads of stage st + 1, own reads of this slot
             __syncthreads();
-            if (st + 2 < nst) issue(b0 + st + 2, slot);
-            if (st + 1 < nst) read(f0, slot ^ 1, 0);
+            issue(min(b0 + st + 2, blast), slot);
+            read(f0, slot ^ 1, 0);
             mma(f1);
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // one global load
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            }
         }
-        __syncthreads();  // ring reads done before the flush reuses the LDS
-        flush();          // FP32 chunk of at most KC k into the FP64 tile
+        __builtin_amdgcn_s_waitcnt(0);  // the last (redundant) refill has landed
+        __syncthreads();                // ring reads done before the flush reuses the LDS
+        flush();                        // FP32 chunk of at most KC k into the FP64 tile
     }
     if (first) flush();
 }
