@@ -228,13 +228,30 @@ __global__ void __launch_bounds__(kThreads) iso_expand_kernel(ExpandParams p, co
                     r[l2] = acc;
                 }
                 if (SPLIT) {
+                    // two consecutive outputs starting at an even offset are
+                    // adjacent in both layouts (row lengths are even), so they
+                    // go out as one 4-byte store per array
+                    bool done = false;
 #pragma unroll
                     for (int l2 = 0; l2 < XP_MAXS; ++l2) {
                         if (l2 >= p.L2) break;
-                        uint16_t h = bf16_bits((float)r[l2]);
+                        if (done) {
+                            done = false;
+                            continue;
+                        }
+                        const uint16_t h = bf16_bits((float)r[l2]);
+                        const uint16_t lw = bf16_bits((float)(r[l2] - bf16_value(h)));
                         const size_t po = split_offset(p, o + l2);
-                        hi[po] = h;
-                        lo[po] = bf16_bits((float)(r[l2] - bf16_value(h)));
+                        if (((o + l2) & 1) == 0 && l2 + 1 < p.L2 && l2 + 1 < XP_MAXS) {
+                            const uint16_t h2 = bf16_bits((float)r[l2 + 1]);
+                            const uint16_t lw2 = bf16_bits((float)(r[l2 + 1] - bf16_value(h2)));
+                            *(uint32_t *)(hi + po) = (uint32_t)h | ((uint32_t)h2 << 16);
+                            *(uint32_t *)(lo + po) = (uint32_t)lw | ((uint32_t)lw2 << 16);
+                            done = true;
+                        } else {
+                            hi[po] = h;
+                            lo[po] = lw;
+                        }
                     }
                 } else {
 #pragma unroll
@@ -264,9 +281,116 @@ __global__ void __launch_bounds__(kThreads) iso_expand_kernel(ExpandParams p, co
     }
 }
 
+// Specialisation for the shapes of the HOTRG step, where the summed index and
+// the second loop index run over the same leg dimension N (nsum == L2 == N):
+// the block first stages the isometry block U[l1, l2, i] (in use order) in
+// LDS, so that the fully unrolled inner loop reads it with wave-uniform LDS
+// loads instead of one dependent scalar load per FMA.  Same arithmetic, in
+// the same order, as iso_expand_kernel.
+template <bool SPLIT, bool RUN, int N>
+__global__ void __launch_bounds__(kThreads) iso_expand_lds_kernel(ExpandParams p, const double *__restrict__ in,
+                                                                  const double *__restrict__ U,
+                                                                  double *__restrict__ out,
+                                                                  uint16_t *__restrict__ hi,
+                                                                  uint16_t *__restrict__ lo) {
+    extern __shared__ double sU[];  // [L1][N][N]
+    const int nU = p.L1 * N * N;
+    for (int idx = threadIdx.x; idx < nU; idx += blockDim.x) {
+        const int i = idx % N, l2 = (idx / N) % N, l1 = idx / (N * N);
+        sU[idx] = U[l1 * p.u1 + l2 * p.u2 + i * p.us];
+    }
+    __syncthreads();
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < p.threads; t += gridDim.x * blockDim.x) {
+        uint32_t rem = t, ib = 0, ob = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.ext[k]);
+            uint32_t c = rem - q * p.ext[k].d;
+            ib += c * p.in_st[k];
+            ob += c * p.out_st[k];
+            rem = q;
+        }
+        double v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = in[ib + i * p.xs];
+        for (int l1 = 0; l1 < p.L1; ++l1) {
+            const double *ul = sU + l1 * N * N;
+            const uint32_t o = ob + l1 * p.o1;
+            // outputs in pairs (l2, l2 + 1): few live registers; a pair that
+            // starts at an even offset of a contiguous run is adjacent in both
+            // layouts (row lengths are even) and goes out as 4-byte stores
+#pragma unroll 1
+            for (int l2 = 0; l2 < N; l2 += 2) {
+                const bool two = l2 + 1 < N;
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    a0 = fma(ul[l2 * N + i], v[i], a0);
+                    if (two) a1 = fma(ul[(l2 + 1) * N + i], v[i], a1);
+                }
+                const uint32_t o0 = RUN ? o + l2 : o + l2 * p.o2;
+                const uint32_t o1 = RUN ? o0 + 1 : o0 + p.o2;
+                if (SPLIT) {
+                    const uint16_t h0 = bf16_bits((float)a0), w0 = bf16_bits((float)(a0 - bf16_value(h0)));
+                    const size_t p0 = split_offset(p, o0);
+                    if (two) {
+                        const uint16_t h1 = bf16_bits((float)a1), w1 = bf16_bits((float)(a1 - bf16_value(h1)));
+                        if (RUN && (o0 & 1) == 0) {
+                            *(uint32_t *)(hi + p0) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                            *(uint32_t *)(lo + p0) = (uint32_t)w0 | ((uint32_t)w1 << 16);
+                        } else {
+                            const size_t p1 = split_offset(p, o1);
+                            hi[p0] = h0;
+                            lo[p0] = w0;
+                            hi[p1] = h1;
+                            lo[p1] = w1;
+                        }
+                    } else {
+                        hi[p0] = h0;
+                        lo[p0] = w0;
+                    }
+                } else {
+                    out[o0] = a0;
+                    if (two) out[o1] = a1;
+                }
+            }
+        }
+    }
+}
+
+template <int N>
+void launch_iso_expand_lds(const ExpandParams &p, const double *in, const double *U, double *out, uint16_t *hi,
+                           uint16_t *lo, hipStream_t s) {
+    const size_t lds = (size_t)p.L1 * N * N * sizeof(double);
+    const int g = grid_for(p.threads, kThreads, 4096);  // blocks loop, so U is staged only 4096 times
+    const bool run = p.o2 == 1;
+    if (hi) {
+        if (run) iso_expand_lds_kernel<true, true, N><<<g, kThreads, lds, s>>>(p, in, U, out, hi, lo);
+        else iso_expand_lds_kernel<true, false, N><<<g, kThreads, lds, s>>>(p, in, U, out, hi, lo);
+    } else {
+        if (run) iso_expand_lds_kernel<false, true, N><<<g, kThreads, lds, s>>>(p, in, U, out, hi, lo);
+        else iso_expand_lds_kernel<false, false, N><<<g, kThreads, lds, s>>>(p, in, U, out, hi, lo);
+    }
+}
+
 void launch_iso_expand(const ExpandParams &p, const double *in, const double *U, double *out, uint16_t *hi,
                        uint16_t *lo, hipStream_t s) {
     if (p.threads == 0) return;
+    if (p.nsum == p.L2 && (size_t)p.L1 * p.L2 * p.L2 * sizeof(double) <= 48 * 1024) {
+        switch (p.L2) {
+            case 2: return launch_iso_expand_lds<2>(p, in, U, out, hi, lo, s);
+            case 3: return launch_iso_expand_lds<3>(p, in, U, out, hi, lo, s);
+            case 4: return launch_iso_expand_lds<4>(p, in, U, out, hi, lo, s);
+            case 5: return launch_iso_expand_lds<5>(p, in, U, out, hi, lo, s);
+            case 6: return launch_iso_expand_lds<6>(p, in, U, out, hi, lo, s);
+            case 7: return launch_iso_expand_lds<7>(p, in, U, out, hi, lo, s);
+            case 8: return launch_iso_expand_lds<8>(p, in, U, out, hi, lo, s);
+            case 9: return launch_iso_expand_lds<9>(p, in, U, out, hi, lo, s);
+            case 10: return launch_iso_expand_lds<10>(p, in, U, out, hi, lo, s);
+            case 11: return launch_iso_expand_lds<11>(p, in, U, out, hi, lo, s);
+            case 12: return launch_iso_expand_lds<12>(p, in, U, out, hi, lo, s);
+            default: break;
+        }
+    }
     const int g = grid_for(p.threads);
     const bool run = p.o2 == 1 && p.L2 > 1;
     if (hi) {
