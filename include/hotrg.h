@@ -55,7 +55,9 @@ typedef struct {
     int mixed_from_step;  /* first step (1-based) whose contraction uses the mixed path; 0 -> 4 */
     double tau_deg;       /* gap threshold of the degenerate-cut rule; 0 -> 1e-12 */
     void *stream;         /* hipStream_t; NULL = default stream */
-    size_t slice_budget;  /* bytes for the contraction operand slices; 0 -> automatic */
+    size_t slice_budget;  /* operand bytes of one K slice above which the contraction
+                             slices also fix the b1' index (one value per slice); 0 ->
+                             only where a slice would exceed 2^31 elements per tensor */
 } hotrg_config;
 
 /* Set up the one-site state of Eqs. (2.2) and (2.6) with bond dimension 2:

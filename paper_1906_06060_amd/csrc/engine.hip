@@ -569,20 +569,30 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     const int Da = D[tv[0]], Db = D[tv[1]], Dc = D[tv[2]], Dm = D[mu];
     const int ka = k[0], kb = k[1], kc = k[2];
     const uint64_t M = (uint64_t)ka * kb * kc * Dm;  // rows of one tensor = columns
-    const uint64_t Ks = (uint64_t)Db * Dc * Da * Db * Dc;
     const bool imp = c->cfg.impurities != 0;
     const bool se_pair = imp && c->n == 0;  // Eq. (2.8): S_e . S_e on the first step
     const int nA = imp ? 3 : 1;
     const int nA_shared = se_pair ? 2 : nA;  // operands multiplying B(T)
-    if (M * (Ks + 63) >= (1ull << 31)) return set_err(HOTRG_ENOMEM, "operand slice exceeds 2^31 elements");
+    const int nB = se_pair ? 2 : 1;
     if (M * M * 3 > c->cap * 3) return set_err(HOTRG_EINVAL, "new tensor exceeds capacity");
     const bool mixed = c->cfg.precision == HOTRG_BF16X3 && (c->n + 1) >= c->cfg.mixed_from_step;
+    // K slices fix (alpha, a1') and, when a slice would exceed 2^31 elements
+    // per tensor or the configured operand budget, also b1' (Eb = 1)
+    auto slice_bytes = [&](uint64_t ks) {
+        const uint64_t l = mixed ? (ks + 63) / 64 * 64 : ks;
+        return mixed ? (uint64_t)4 * packed_rows(M) * l * (nA + nB) : (uint64_t)8 * M * l * (nA + nB);
+    };
+    const uint64_t Ks2 = (uint64_t)Db * Dc * Da * Db * Dc;
+    const bool slice_b = M * (Ks2 + 63) >= (1ull << 31) ||
+                         (c->cfg.slice_budget > 0 && slice_bytes(Ks2) > c->cfg.slice_budget);
+    const int Eb = slice_b ? 1 : Db;  // b1' values inside one slice
+    const uint64_t Ks = (uint64_t)Eb * Dc * Da * Db * Dc;
+    if (M * (Ks + 63) >= (1ull << 31)) return set_err(HOTRG_ENOMEM, "operand slice exceeds 2^31 elements");
     // bf16 operand rows are padded with zero columns to a multiple of the
     // 64 k the kernel stages at a time
     const uint64_t ld = mixed ? (Ks + 63) / 64 * 64 : Ks;
     const uint64_t slice = M * ld;          // row-major operand slice of one tensor
     const uint64_t pslice = packed_rows(M) * ld;  // the same in the packed bf16 layout
-    const int nB = se_pair ? 2 : 1;
     double *Asl = nullptr, *Bsl = nullptr;
     uint16_t *Ah = nullptr, *Al = nullptr, *Bh = nullptr, *Bl = nullptr;
     if (mixed) {
@@ -608,17 +618,18 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     // part outermost in GEMM order, so every read is a contiguous run):
     //   Y1[a, mu1, b1', c1', a2, c1, b1]        Y2[a, b, mu1, b1', c1', a2, b2, c1]
     //   Z1[a', mu2', a2, b2, c2, c2', b2']      Z2[a', b', mu2', b1', a2, b2, c2, c2']
-    // GEMM rows (a, b, mu1, c), columns (a', b', mu2', c'), K (b1', c1', a2, b2, c2).
-    const int y1e[7] = {ka, Dm, Db, Dc, Da, Dc, Db};
+    // GEMM rows (a, b, mu1, c), columns (a', b', mu2', c'), K (b1', c1', a2, b2, c2);
+    // b1' runs over Eb values (a slice may fix it).
+    const int y1e[7] = {ka, Dm, Eb, Dc, Da, Dc, Db};
     uint64_t y1s[7];
     row_major_strides(7, y1e, y1s);
-    const int y2e[8] = {ka, kb, Dm, Db, Dc, Da, Db, Dc};
+    const int y2e[8] = {ka, kb, Dm, Eb, Dc, Da, Db, Dc};
     uint64_t y2s[8];
     row_major_strides(8, y2e, y2s);
     const int z1e[7] = {ka, Dm, Da, Db, Dc, Dc, Db};
     uint64_t z1s[7];
     row_major_strides(7, z1e, z1s);
-    const int z2e[8] = {ka, kb, Dm, Db, Da, Db, Dc, Dc};
+    const int z2e[8] = {ka, kb, Dm, Eb, Da, Db, Dc, Dc};
     uint64_t z2s[8];
     row_major_strides(8, z2e, z2s);
 
@@ -629,15 +640,16 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
 
     bool first_slice = true;
     for (int g = 0; g < Dm; ++g) {       // alpha
-        for (int f = 0; f < Da; ++f) {   // a1'
+      for (int f = 0; f < Da; ++f) {     // a1'
+        for (int e0 = 0; e0 < Db; e0 += Eb) {  // first b1' of the slice
             // ---- A rows: T1 in {T, S_m, S_e}
             for (int t = 0; t < nA; ++t) {
-                const uint64_t off = f * lst[1] + g * lst[7];
+                const uint64_t off = f * lst[1] + g * lst[7] + e0 * lst[3];
                 const double *X1 = c->state[t] + off;
                 {   // P1: Y1[a,mu1,b1',c1',a2,c1,b1] = sum_a1 Ua[(a1,a2),a] T1[a1,f,b1,b1',c1,c1',mu1,g]
                     XP x;
                     x.tdim(Dm, lst[6], y1s[1]);
-                    x.tdim(Db, lst[3], y1s[2]);
+                    x.tdim(Eb, lst[3], y1s[2]);
                     x.tdim(Dc, lst[5], y1s[3]);
                     x.tdim(Dc, lst[4], y1s[5]);
                     x.tdim(Db, lst[2], y1s[6]);
@@ -650,7 +662,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     XP x;
                     x.tdim(ka, y1s[0], y2s[0]);
                     x.tdim(Dm, y1s[1], y2s[2]);
-                    x.tdim(Db, y1s[2], y2s[3]);
+                    x.tdim(Eb, y1s[2], y2s[3]);
                     x.tdim(Dc, y1s[3], y2s[4]);
                     x.tdim(Da, y1s[4], y2s[5]);
                     x.tdim(Dc, y1s[5], y2s[7]);
@@ -664,7 +676,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.tdim(ka, y2s[0], rs0);
                     x.tdim(kb, y2s[1], rs1);
                     x.tdim(Dm, y2s[2], rs2);
-                    x.tdim(Db, y2s[3], ks0);
+                    x.tdim(Eb, y2s[3], ks0);
                     x.tdim(Dc, y2s[4], ks1);
                     x.tdim(Da, y2s[5], ks2);
                     x.tdim(Db, y2s[6], ks3);
@@ -705,17 +717,18 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.tdim(Db, z1s[3], z2s[5]);
                     x.tdim(Dc, z1s[4], z2s[6]);
                     x.tdim(Dc, z1s[5], z2s[7]);
-                    x.loops(kb, 1, z2s[1], Db, (uint64_t)Db * kb, z2s[3]);
+                    x.loops(kb, 1, z2s[1], Eb, (uint64_t)Db * kb, z2s[3]);
                     x.sum(Db, z1s[6], kb);
-                    if (!x.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "Q2 launch out of bounds");
-                    launch_iso_expand(x.done(), c->y1, Ub, c->y2, nullptr, nullptr, c->stream);
+                    const uint64_t uoff = (uint64_t)e0 * Db * kb;  // rows (b1' = e0, b2') of Ub
+                    if (!x.fits(c->cap, usz[1] - uoff, c->cap)) return set_err(HOTRG_EINVAL, "Q2 launch out of bounds");
+                    launch_iso_expand(x.done(), c->y1, Ub + uoff, c->y2, nullptr, nullptr, c->stream);
                 }
                 {   // Q3: Bt[(a',b',mu2',c'),(b1',c1',a2,b2,c2)] = sum_c2' Uc[(c1',c2'),c'] Z2
                     XP x;
                     x.tdim(ka, z2s[0], rs0);
                     x.tdim(kb, z2s[1], rs1);
                     x.tdim(Dm, z2s[2], rs2);
-                    x.tdim(Db, z2s[3], ks0);
+                    x.tdim(Eb, z2s[3], ks0);
                     x.tdim(Da, z2s[4], ks2);
                     x.tdim(Db, z2s[5], ks3);
                     x.tdim(Dc, z2s[6], 1);
@@ -750,6 +763,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
             first_slice = false;
             TRY(check_launch(c, "contraction slice"));
         }
+      }
     }
     return HOTRG_OK;
 }

@@ -149,10 +149,11 @@ class Context:
     """One HOTRG coarse-graining state on the GPU (hotrg_ctx)."""
 
     def __init__(self, beta: float, h: float, dcut: int, precision: int = FP64, impurities: bool = True,
-                 keep_checkpoints: bool = False, mixed_from_step: int = 0, tau_deg: float = 0.0, stream=None):
+                 keep_checkpoints: bool = False, mixed_from_step: int = 0, tau_deg: float = 0.0, stream=None,
+                 slice_budget: int = 0):
         lib = load()
         cfg = Config(precision, int(impurities), int(keep_checkpoints), mixed_from_step, tau_deg,
-                     stream if stream is not None else _current_stream(), 0)
+                     stream if stream is not None else _current_stream(), slice_budget)
         self._h = C.c_void_p()
         self.beta, self.h, self.dcut = beta, h, dcut
         self.impurities = impurities

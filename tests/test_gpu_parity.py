@@ -66,7 +66,9 @@ CASES = [
 
 @pytest.mark.parametrize("dims,dcut,axis,ks", CASES)
 @pytest.mark.parametrize("n0", [0, 3])
-def test_contraction_full_tensor_fp64(H, dims, dcut, axis, ks, n0):
+@pytest.mark.parametrize("budget", [0, 1])
+def test_contraction_full_tensor_fp64(H, dims, dcut, axis, ks, n0, budget):
+    # budget = 1 byte forces K slices that also fix b1' (one b1' value each)
     T = synth.z2_tensor(dims, seed=101)
     Sm = synth.z2_tensor(dims, seed=102, odd=True)
     Se = synth.z2_tensor(dims, seed=103)
@@ -76,7 +78,7 @@ def test_contraction_full_tensor_fp64(H, dims, dcut, axis, ks, n0):
         n = dims[q] ** 2
         k = min(dcut, n) if ks is None else ks[j]
         Us[q] = synth.isometry(n, k, seed=200 + q)
-    with H.Context(0.2, 0.0, dcut) as ctx:
+    with H.Context(0.2, 0.0, dcut, slice_budget=budget) as ctx:
         ctx.set_state(T, Sm, Se, n=n0, lnz_acc=0.0)
         ctx.step_with_isometries(axis, Us)
         got = [ctx.tensor(w) for w in range(3)]
@@ -91,14 +93,15 @@ def test_contraction_full_tensor_fp64(H, dims, dcut, axis, ks, n0):
         np.testing.assert_allclose(g, w, rtol=0, atol=1e-13 * max(np.abs(w).max(), 1e-300))
 
 
-def _sampled_parity(H, D, axis, precision, impurities, nrows, bound, seed=7):
+def _sampled_parity(H, D, axis, precision, impurities, nrows, bound, seed=7, slice_budget=0):
     dims = (D, D, D, D)
     T = synth.z2_tensor(dims, seed=seed)
     Sm = synth.z2_tensor(dims, seed=seed + 1, odd=True) if impurities else None
     Se = synth.z2_tensor(dims, seed=seed + 2) if impurities else None
     tv = [q for q in range(4) if q != axis]
     Us = {q: synth.isometry(D * D, D, seed=seed + 10 + q) for q in tv}
-    with H.Context(0.2, 0.0, D, precision=precision, impurities=impurities, mixed_from_step=1) as ctx:
+    with H.Context(0.2, 0.0, D, precision=precision, impurities=impurities, mixed_from_step=1,
+                   slice_budget=slice_budget) as ctx:
         ctx.set_state(T, Sm, Se, n=4, lnz_acc=0.0)
         ctx.step_with_isometries(axis, Us)
         cn = ctx.observables()["last_cn"]
@@ -134,6 +137,12 @@ def test_contraction_sampled_d8_bf16x3(H, axis):
     # chunks of 8192 k: bounded by 6e-5 |row| |col| (Cauchy-Schwarz)
     w = _sampled_parity(H, 8, axis, H.BF16X3, True, 24, 6e-5)
     print(f"bf16x3 D=8 worst scaled error {w:.3e}")
+
+
+def test_contraction_sampled_d8_bf16x3_b1_slices(H):
+    # slices that also fix b1' (as at Dcut = 12, where two fixed indices leave
+    # more than 2^31 operand elements per tensor), forced by a 1-byte budget
+    _sampled_parity(H, 8, 2, H.BF16X3, True, 16, 6e-5, seed=11, slice_budget=1)
 
 
 def test_contraction_sampled_d10_bf16x3_bench_configuration(H):
