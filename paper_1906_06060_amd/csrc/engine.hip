@@ -124,7 +124,7 @@ struct hotrg_ctx {
     bool ckpt_broken = false;
     double c0 = 1.0;
     // reverse-pass work buffers
-    DevBuf bw[12];
+    DevBuf bw[13];
 };
 
 namespace {
@@ -931,7 +931,8 @@ int read_obs(hotrg_ctx *c, double *tr, double *trm, double *tre, std::vector<dou
 // ======================================================= reverse pass ====
 // Work buffers of the reverse pass (grown on demand, kept for later calls).
 enum {
-    BW_TBAR0, BW_TBAR1, BW_CBAR, BW_CBART, BW_AT, BW_BT, BW_ABAR, BW_BBAR, BW_Z1, BW_Z2, BW_YB1, BW_YB2
+    BW_TBAR0, BW_TBAR1, BW_CBAR, BW_CBART, BW_AT, BW_BT, BW_ABAR, BW_BBAR, BW_Z1, BW_Z2, BW_YB1, BW_YB2,
+    BW_X3  // packed bf16 hi / lo of C_bar, C_bar^T, A^T, B^T (mixed precision)
 };
 
 template <typename T>
@@ -956,7 +957,7 @@ int run_einsum(hotrg_ctx *c, EP &e, const double *X, uint64_t xa, const double *
 // A_bar_s = C_bar B_s and B_bar_s = C_bar^T A_s, which flow back through the
 // isometry products into T and the isometries; the isometries flow back
 // through the eigendecomposition and the environments into T.
-int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *Tbar, double *Tprev) {
+int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *Tbar, double *Tprev, bool mixed) {
     const int *D = cp.dims;
     const int mu = cp.axis;
     const int *tv = cp.tv;
@@ -975,7 +976,13 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
     const int Da = D[tv[0]], Db = D[tv[1]], Dc = D[tv[2]], Dm = D[mu];
     const int ka = cp.k[0], kb = cp.k[1], kc = cp.k[2];
     const uint64_t M = (uint64_t)ka * kb * Dm * kc;  // rows = columns of C
-    const uint64_t Ks = (uint64_t)Db * Dc * Da * Db * Dc;
+    // K slices as in the forward: (alpha, a1') fixed, and b1' too (Eb = 1)
+    // where a two-index slice exceeds 2^31 elements or the operand budget
+    const uint64_t Ks2 = (uint64_t)Db * Dc * Da * Db * Dc;
+    const bool slice_b = M * Ks2 >= (1ull << 31) ||
+                         (c->cfg.slice_budget > 0 && (uint64_t)4 * 8 * M * Ks2 > c->cfg.slice_budget);
+    const int Eb = slice_b ? 1 : Db;
+    const uint64_t Ks = (uint64_t)Eb * Dc * Da * Db * Dc;
     const uint64_t tsize = tensor_size(D);
     const double *T = cp.T;
     const double *Ua = cp.U[0], *Ub = cp.U[1], *Uc = cp.U[2];
@@ -983,11 +990,34 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
     if (M * Ks >= (1ull << 31) || M * M >= (1ull << 31))
         return set_err(HOTRG_ENOMEM, "reverse pass: operand slice exceeds 2^31 elements");
 
-    double *Cbar, *CbarT, *AT, *BT, *Abar, *Bbar, *Z1, *Z2, *Yb1, *Yb2;
+    double *Cbar, *CbarT, *AT = nullptr, *BT = nullptr, *Abar, *Bbar, *Z1, *Z2, *Yb1, *Yb2;
     TRY(bw_buf(c, BW_CBAR, M * M, &Cbar));
     TRY(bw_buf(c, BW_CBART, M * M, &CbarT));
-    TRY(bw_buf(c, BW_AT, M * Ks, &AT));
-    TRY(bw_buf(c, BW_BT, M * Ks, &BT));
+    // mixed precision: the reverse GEMMs run as bf16x3 products on packed
+    // operands with row length ldM (the recomputed A^T, B^T go there directly)
+    const uint64_t ldM = mixed ? (M + 63) / 64 * 64 : M;  // row length of A^T, B^T (and C_bar splits)
+    const uint64_t pC = packed_rows(M) * ldM, pK = packed_rows(Ks) * ldM;
+    uint16_t *Ch = nullptr, *Cl = nullptr, *CTh = nullptr, *CTl = nullptr;
+    uint16_t *ATh = nullptr, *ATl = nullptr, *BTh = nullptr, *BTl = nullptr;
+    if (mixed) {
+        if (M * ldM >= (1ull << 32) || Ks * ldM >= (1ull << 31))
+            return set_err(HOTRG_ENOMEM, "reverse pass: packed operand exceeds 2^31 elements");
+        uint16_t *x3;
+        TRY(bw_buf(c, BW_X3, 4 * pC + 4 * pK, &x3));
+        Ch = x3;
+        Cl = Ch + pC;
+        CTh = Cl + pC;
+        CTl = CTh + pC;
+        ATh = CTl + pC;
+        ATl = ATh + pK;
+        BTh = ATl + pK;
+        BTl = BTh + pK;
+        // padding columns of A^T, B^T are never written by the products
+        if (ldM != M) HIP_TRY(c, hipMemsetAsync(ATh, 0, sizeof(uint16_t) * 4 * pK, c->stream));
+    } else {
+        TRY(bw_buf(c, BW_AT, M * Ks, &AT));
+        TRY(bw_buf(c, BW_BT, M * Ks, &BT));
+    }
     TRY(bw_buf(c, BW_ABAR, M * Ks, &Abar));
     TRY(bw_buf(c, BW_BBAR, M * Ks, &Bbar));
     TRY(bw_buf(c, BW_Z1, c->cap, &Z1));
@@ -1018,19 +1048,23 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
         uint32_t stT[8] = {st[4], st[5], st[6], st[7], st[0], st[1], st[2], st[3]};
         pp = perm_params(8, ext, stT, &mx);
         launch_permute(pp, Tbar, CbarT, 1.0 / cp.c, c->stream);
+        if (mixed) {
+            launch_split_pack(Cbar, (uint32_t)M, (uint32_t)M, (uint32_t)ldM, Ch, Cl, c->stream);
+            launch_split_pack(CbarT, (uint32_t)M, (uint32_t)M, (uint32_t)ldM, CTh, CTl, c->stream);
+        }
         TRY(check_launch(c, "C_bar"));
     }
 
-    const int y1e[7] = {ka, Dm, Db, Dc, Da, Dc, Db};
+    const int y1e[7] = {ka, Dm, Eb, Dc, Da, Dc, Db};
     uint64_t y1s[7];
     row_major_strides(7, y1e, y1s);
-    const int y2e[8] = {ka, kb, Dm, Db, Dc, Da, Db, Dc};
+    const int y2e[8] = {ka, kb, Dm, Eb, Dc, Da, Db, Dc};
     uint64_t y2s[8];
     row_major_strides(8, y2e, y2s);
     const int z1e[7] = {ka, Dm, Da, Db, Dc, Dc, Db};
     uint64_t z1s[7];
     row_major_strides(7, z1e, z1s);
-    const int z2e[8] = {ka, kb, Dm, Db, Da, Db, Dc, Dc};
+    const int z2e[8] = {ka, kb, Dm, Eb, Da, Db, Dc, Dc};
     uint64_t z2s[8];
     row_major_strides(8, z2e, z2s);
     const uint64_t ks0 = (uint64_t)Dc * Da * Db * Dc, ks1 = (uint64_t)Da * Db * Dc, ks2 = (uint64_t)Db * Dc,
@@ -1039,14 +1073,16 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
     const uint64_t r0 = (uint64_t)kb * Dm * kc, r1 = (uint64_t)Dm * kc, r2 = kc;
 
     for (int g = 0; g < Dm; ++g) {
-        for (int f = 0; f < Da; ++f) {
-            const uint64_t offA = f * lst[1] + g * lst[7];
+      for (int f = 0; f < Da; ++f) {
+        for (int e0 = 0; e0 < Db; e0 += Eb) {  // first b1' of the slice
+            const uint64_t offA = f * lst[1] + g * lst[7] + e0 * lst[3];
             const uint64_t offB = g * lst[6];
+            const uint64_t uboff = (uint64_t)e0 * Db * kb;  // rows (b1' = e0, b2') of Ub
             // ---- recompute the forward intermediates and the operands, transposed ([K][rows])
             {
                 XP x;  // P1
                 x.tdim(Dm, lst[6], y1s[1]);
-                x.tdim(Db, lst[3], y1s[2]);
+                x.tdim(Eb, lst[3], y1s[2]);
                 x.tdim(Dc, lst[5], y1s[3]);
                 x.tdim(Dc, lst[4], y1s[5]);
                 x.tdim(Db, lst[2], y1s[6]);
@@ -1059,7 +1095,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 XP x;  // P2
                 x.tdim(ka, y1s[0], y2s[0]);
                 x.tdim(Dm, y1s[1], y2s[2]);
-                x.tdim(Db, y1s[2], y2s[3]);
+                x.tdim(Eb, y1s[2], y2s[3]);
                 x.tdim(Dc, y1s[3], y2s[4]);
                 x.tdim(Da, y1s[4], y2s[5]);
                 x.tdim(Dc, y1s[5], y2s[7]);
@@ -1069,18 +1105,23 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 launch_iso_expand(x.done(), Y1, Ub, Y2, nullptr, nullptr, c->stream);
             }
             {
-                XP x;  // P3 -> A^T [K][M]
+                XP x;  // P3 -> A^T [K][M] (row length ldM)
                 x.tdim(ka, y2s[0], r0);
                 x.tdim(kb, y2s[1], r1);
                 x.tdim(Dm, y2s[2], r2);
-                x.tdim(Db, y2s[3], ks0 * M);
-                x.tdim(Dc, y2s[4], ks1 * M);
-                x.tdim(Da, y2s[5], ks2 * M);
-                x.tdim(Db, y2s[6], ks3 * M);
-                x.loops(kc, 1, 1, Dc, kc, M);
+                x.tdim(Eb, y2s[3], ks0 * ldM);
+                x.tdim(Dc, y2s[4], ks1 * ldM);
+                x.tdim(Da, y2s[5], ks2 * ldM);
+                x.tdim(Db, y2s[6], ks3 * ldM);
+                x.loops(kc, 1, 1, Dc, kc, ldM);
                 x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
-                if (!x.fits(c->cap, usz[2], M * Ks)) return set_err(HOTRG_EINVAL, "bw P3 out of bounds");
-                launch_iso_expand(x.done(), Y2, Uc, AT, nullptr, nullptr, c->stream);
+                if (!x.fits(c->cap, usz[2], ldM * Ks)) return set_err(HOTRG_EINVAL, "bw P3 out of bounds");
+                if (mixed) {
+                    x.packed(ldM);
+                    launch_iso_expand(x.done(), Y2, Uc, nullptr, ATh, ATl, c->stream);
+                } else {
+                    launch_iso_expand(x.done(), Y2, Uc, AT, nullptr, nullptr, c->stream);
+                }
             }
             {
                 XP x;  // Q1
@@ -1104,28 +1145,38 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 x.tdim(Db, z1s[3], z2s[5]);
                 x.tdim(Dc, z1s[4], z2s[6]);
                 x.tdim(Dc, z1s[5], z2s[7]);
-                x.loops(kb, 1, z2s[1], Db, (uint64_t)Db * kb, z2s[3]);
+                x.loops(kb, 1, z2s[1], Eb, (uint64_t)Db * kb, z2s[3]);
                 x.sum(Db, z1s[6], kb);
-                if (!x.fits(c->cap, usz[1], c->cap)) return set_err(HOTRG_EINVAL, "bw Q2 out of bounds");
-                launch_iso_expand(x.done(), Z1, Ub, Z2, nullptr, nullptr, c->stream);
+                if (!x.fits(c->cap, usz[1] - uboff, c->cap)) return set_err(HOTRG_EINVAL, "bw Q2 out of bounds");
+                launch_iso_expand(x.done(), Z1, Ub + uboff, Z2, nullptr, nullptr, c->stream);
             }
             {
-                XP x;  // Q3 -> B^T [K][N]
+                XP x;  // Q3 -> B^T [K][N] (row length ldM)
                 x.tdim(ka, z2s[0], r0);
                 x.tdim(kb, z2s[1], r1);
                 x.tdim(Dm, z2s[2], r2);
-                x.tdim(Db, z2s[3], ks0 * M);
-                x.tdim(Da, z2s[4], ks2 * M);
-                x.tdim(Db, z2s[5], ks3 * M);
-                x.tdim(Dc, z2s[6], M);
-                x.loops(kc, 1, 1, Dc, (uint64_t)Dc * kc, ks1 * M);
+                x.tdim(Eb, z2s[3], ks0 * ldM);
+                x.tdim(Da, z2s[4], ks2 * ldM);
+                x.tdim(Db, z2s[5], ks3 * ldM);
+                x.tdim(Dc, z2s[6], ldM);
+                x.loops(kc, 1, 1, Dc, (uint64_t)Dc * kc, ks1 * ldM);
                 x.sum(Dc, z2s[7], kc);
-                if (!x.fits(c->cap, usz[2], M * Ks)) return set_err(HOTRG_EINVAL, "bw Q3 out of bounds");
-                launch_iso_expand(x.done(), Z2, Uc, BT, nullptr, nullptr, c->stream);
+                if (!x.fits(c->cap, usz[2], ldM * Ks)) return set_err(HOTRG_EINVAL, "bw Q3 out of bounds");
+                if (mixed) {
+                    x.packed(ldM);
+                    launch_iso_expand(x.done(), Z2, Uc, nullptr, BTh, BTl, c->stream);
+                } else {
+                    launch_iso_expand(x.done(), Z2, Uc, BT, nullptr, nullptr, c->stream);
+                }
             }
-            // ---- A_bar = C_bar B, B_bar = C_bar^T A  (FP64 MFMA)
-            launch_gemm_f64(Cbar, BT, Abar, (int)M, (int)Ks, (int)M, M, M, Ks, 0, c->stream);
-            launch_gemm_f64(CbarT, AT, Bbar, (int)M, (int)Ks, (int)M, M, M, Ks, 0, c->stream);
+            // ---- A_bar = C_bar B, B_bar = C_bar^T A (FP64, or bf16x3 in mixed precision)
+            if (mixed) {
+                launch_gemm_bf16x3(Ch, Cl, BTh, BTl, Abar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream);
+                launch_gemm_bf16x3(CTh, CTl, ATh, ATl, Bbar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream);
+            } else {
+                launch_gemm_f64(Cbar, BT, Abar, (int)M, (int)Ks, (int)M, M, M, Ks, 0, c->stream);
+                launch_gemm_f64(CbarT, AT, Bbar, (int)M, (int)Ks, (int)M, M, M, Ks, 0, c->stream);
+            }
             TRY(check_launch(c, "reverse GEMMs"));
 
             // ---- A side: through P3, P2, P1
@@ -1134,7 +1185,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.o(ka, r0 * Ks, 0, y2s[0]);
                 e.o(kb, r1 * Ks, 0, y2s[1]);
                 e.o(Dm, r2 * Ks, 0, y2s[2]);
-                e.o(Db, ks0, 0, y2s[3]);
+                e.o(Eb, ks0, 0, y2s[3]);
                 e.o(Dc, ks1, 0, y2s[4]);
                 e.o(Da, ks2, 0, y2s[5]);
                 e.o(Db, ks3, 0, y2s[6]);
@@ -1151,7 +1202,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.s(ka, y2s[0], r0 * Ks);
                 e.s(kb, y2s[1], r1 * Ks);
                 e.s(Dm, y2s[2], r2 * Ks);
-                e.s(Db, y2s[3], ks0);
+                e.s(Eb, y2s[3], ks0);
                 e.s(Dc, y2s[4], ks1);
                 e.s(Da, y2s[5], ks2);
                 e.s(Db, y2s[6], ks3);
@@ -1161,7 +1212,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 EP e;
                 e.o(ka, y2s[0], 0, y1s[0]);
                 e.o(Dm, y2s[2], 0, y1s[1]);
-                e.o(Db, y2s[3], 0, y1s[2]);
+                e.o(Eb, y2s[3], 0, y1s[2]);
                 e.o(Dc, y2s[4], 0, y1s[3]);
                 e.o(Da, y2s[5], 0, y1s[4]);
                 e.o(Dc, y2s[7], 0, y1s[5]);
@@ -1177,7 +1228,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.o(kb, 0, y2s[1], 1);
                 e.s(ka, y1s[0], y2s[0]);
                 e.s(Dm, y1s[1], y2s[2]);
-                e.s(Db, y1s[2], y2s[3]);
+                e.s(Eb, y1s[2], y2s[3]);
                 e.s(Dc, y1s[3], y2s[4]);
                 e.s(Da, y1s[4], y2s[5]);
                 e.s(Dc, y1s[5], y2s[7]);
@@ -1187,7 +1238,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 EP e;
                 e.o(Da, 0, (uint64_t)Da * ka, lst[0]);
                 e.o(Db, y1s[6], 0, lst[2]);
-                e.o(Db, y1s[2], 0, lst[3]);
+                e.o(Eb, y1s[2], 0, lst[3]);
                 e.o(Dc, y1s[5], 0, lst[4]);
                 e.o(Dc, y1s[3], 0, lst[5]);
                 e.o(Dm, y1s[1], 0, lst[6]);
@@ -1201,7 +1252,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.o(Da, 0, y1s[4], ka);
                 e.o(ka, 0, y1s[0], 1);
                 e.s(Dm, lst[6], y1s[1]);
-                e.s(Db, lst[3], y1s[2]);
+                e.s(Eb, lst[3], y1s[2]);
                 e.s(Dc, lst[5], y1s[3]);
                 e.s(Dc, lst[4], y1s[5]);
                 e.s(Db, lst[2], y1s[6]);
@@ -1213,7 +1264,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.o(ka, r0 * Ks, 0, z2s[0]);
                 e.o(kb, r1 * Ks, 0, z2s[1]);
                 e.o(Dm, r2 * Ks, 0, z2s[2]);
-                e.o(Db, ks0, 0, z2s[3]);
+                e.o(Eb, ks0, 0, z2s[3]);
                 e.o(Da, ks2, 0, z2s[4]);
                 e.o(Db, ks3, 0, z2s[5]);
                 e.o(Dc, 1, 0, z2s[6]);
@@ -1230,7 +1281,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.s(ka, z2s[0], r0 * Ks);
                 e.s(kb, z2s[1], r1 * Ks);
                 e.s(Dm, z2s[2], r2 * Ks);
-                e.s(Db, z2s[3], ks0);
+                e.s(Eb, z2s[3], ks0);
                 e.s(Da, z2s[4], ks2);
                 e.s(Db, z2s[5], ks3);
                 e.s(Dc, z2s[6], 1);
@@ -1246,12 +1297,12 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.o(Dc, z2s[7], 0, z1s[5]);
                 e.o(Db, 0, kb, z1s[6]);
                 e.s(kb, z2s[1], 1);
-                e.s(Db, z2s[3], (uint64_t)Db * kb);
-                TRY(run_einsum(c, e, Yb2, c->cap, Ub, usz[1], Yb1, c->cap, 1.0, 0, "bw Z1bar"));
+                e.s(Eb, z2s[3], (uint64_t)Db * kb);
+                TRY(run_einsum(c, e, Yb2, c->cap, Ub + uboff, usz[1] - uboff, Yb1, c->cap, 1.0, 0, "bw Z1bar"));
             }
             {   // Ub_bar[(b1',b2'),b'] += sum Z1[.., b2'] Zb2[.., b', .., b1', ..]
                 EP e;
-                e.o(Db, 0, z2s[3], (uint64_t)Db * kb);
+                e.o(Eb, 0, z2s[3], (uint64_t)Db * kb);
                 e.o(Db, z1s[6], 0, kb);
                 e.o(kb, 0, z2s[1], 1);
                 e.s(ka, z1s[0], z2s[0]);
@@ -1260,7 +1311,8 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.s(Db, z1s[3], z2s[5]);
                 e.s(Dc, z1s[4], z2s[6]);
                 e.s(Dc, z1s[5], z2s[7]);
-                TRY(run_einsum(c, e, Z1, c->cap, Yb2, c->cap, Ubar[1], usz[1], 1.0, 1, "bw Ub_bar (B)"));
+                TRY(run_einsum(c, e, Z1, c->cap, Yb2, c->cap, Ubar[1] + uboff, usz[1] - uboff, 1.0, 1,
+                               "bw Ub_bar (B)"));
             }
             {   // Tprev[a2,a2',b2,b2',c2,c2',g,mu2'] += sum_{a'} Ua[(f,a2'),a'] Zb1[a',mu2',a2,b2,c2,c2',b2']
                 EP e;
@@ -1289,6 +1341,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                                usz[0] - (uint64_t)f * Da * ka, 1.0, 1, "bw Ua_bar (B)"));
             }
         }
+      }
     }
 
     // ---- isometries -> environments -> T (truncated axes only)
@@ -1369,7 +1422,9 @@ int backward(hotrg_ctx *c, double *dbeta, double *dh) {
     launch_zero(Tb, tensor_size(c->dims), c->stream);
     launch_diag_set(Tb, c->dims, dst, std::ldexp(1.0 / tr, -c->n), c->stream);
     for (int k = c->n - 1; k >= 0; --k) {
-        TRY(backward_step(c, c->ckpts[k], Tb, Tp));
+        // the precision of step k + 1 in the forward flow
+        const bool mixed = c->cfg.precision == HOTRG_BF16X3 && (k + 1) >= c->cfg.mixed_from_step;
+        TRY(backward_step(c, c->ckpts[k], Tb, Tp, mixed));
         std::swap(Tb, Tp);
     }
     // d T^(0) / d(beta, h): W[0] = (sqrt cosh b, sqrt sinh b), V = e^{+-b h}

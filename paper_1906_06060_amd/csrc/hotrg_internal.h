@@ -144,6 +144,11 @@ void launch_env_combine(const double *G1, const double *G2, int Dp, int Dq, int 
                         hipStream_t s);
 void launch_identity(double *U, int n, hipStream_t s);
 void launch_zero(double *x, size_t n, hipStream_t s);
+// X[R][K] (FP64, row stride K) -> bf16 hi / lo splits in the packed layout of
+// launch_gemm_bf16x3 with row length ld (a multiple of 64, >= K; padding
+// columns written as zero).  R * ld < 2^32.
+void launch_split_pack(const double *X, uint32_t R, uint32_t K, uint32_t ld, uint16_t *hi, uint16_t *lo,
+                       hipStream_t s);
 
 // reverse pass (kernels_adjoint.hip)
 void launch_einsum(EinsumParams p, const double *X, const double *Y, double *out, double *partial,

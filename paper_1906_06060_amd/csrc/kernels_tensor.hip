@@ -635,6 +635,30 @@ __global__ void zero_kernel(double *x, size_t n) {
         x[i] = 0.0;
 }
 
+// FP64 rows [R][K] (row stride K) -> bf16 hi / lo in the packed GEMM layout
+// with row length ld >= K; the padding columns K .. ld - 1 are written as 0.
+__global__ void __launch_bounds__(kThreads) split_pack_kernel(const double *__restrict__ X, uint32_t R, uint32_t K,
+                                                              FastDiv ld, uint32_t pkb, uint16_t *__restrict__ hi,
+                                                              uint16_t *__restrict__ lo) {
+    const size_t total = (size_t)R * ld.d;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t r = (uint32_t)(idx / ld.d), k = (uint32_t)(idx - (size_t)r * ld.d);
+        const double v = k < K ? X[(size_t)r * K + k] : 0.0;
+        const uint16_t h = bf16_bits((float)v);
+        const size_t po = ((size_t)(r / PACK_ROWS) * pkb + k / PACK_K) * (PACK_ROWS * PACK_K) +
+                          (r % PACK_ROWS) * PACK_K + k % PACK_K;
+        hi[po] = h;
+        lo[po] = bf16_bits((float)(v - bf16_value(h)));
+    }
+}
+
+void launch_split_pack(const double *X, uint32_t R, uint32_t K, uint32_t ld, uint16_t *hi, uint16_t *lo,
+                       hipStream_t s) {
+    if (R == 0 || ld == 0) return;
+    split_pack_kernel<<<grid_for((size_t)R * ld), kThreads, 0, s>>>(X, R, K, make_fastdiv(ld), ld / PACK_K, hi, lo);
+}
+
 void launch_zero(double *x, size_t n, hipStream_t s) {
     if (n == 0) return;
     zero_kernel<<<grid_for(n), kThreads, 0, s>>>(x, n);

@@ -59,6 +59,37 @@ def test_backward_matches_oracle_tangent(H, beta, h, dcut, nsteps):
     assert dh == pytest.approx(th[2], rel=1e-8, abs=1e-13)
 
 
+def test_backward_with_b1_slices_matches_oracle_tangent(H):
+    # a 1-byte operand budget makes the forward and the reverse contraction
+    # slice over b1' as well (the Dcut = 12 layout); same oracle tangent
+    beta, h, dcut, nsteps = 0.1497, 0.02, 4, 6
+    lnz, db, dh = gpu_grad(H, beta, h, dcut, nsteps, slice_budget=1)
+    tb = OT.run(beta, h, dcut, 4, nsteps, "beta")[-1]
+    assert lnz == pytest.approx(tb[1], rel=1e-11)
+    assert db == pytest.approx(tb[2], rel=1e-9)
+    th = OT.run(beta, h, dcut, 4, nsteps, "h")[-1]
+    assert dh == pytest.approx(th[2], rel=1e-8, abs=1e-13)
+
+
+@pytest.mark.parametrize("budget", [0, 1])
+def test_backward_mixed_precision_against_fp64(H, budget):
+    # bf16x3 forward and reverse GEMMs from step 4 on (the FP64 flow's
+    # derivatives are pinned to the oracle tangent above).  Measured at this
+    # point: lnZ/N 1.5e-6, d/dbeta 2.7e-5, d/dh 6.3e-5 relative -- the size of
+    # the forward flow's own mixed-precision error on e and m near beta_c
+    # (up to ~5e-4 relative on m); bounds at about 7-15x that
+    beta, h, dcut, nsteps = 0.1497, 1e-3, 6, 8
+    ref = gpu_grad(H, beta, h, dcut, nsteps, slice_budget=budget)
+    mix = gpu_grad(H, beta, h, dcut, nsteps, precision=H.BF16X3, mixed_from_step=4, slice_budget=budget)
+    dl = abs(mix[0] - ref[0]) / abs(ref[0])
+    db = abs(mix[1] - ref[1]) / abs(ref[1])
+    dh = abs(mix[2] - ref[2]) / abs(ref[2])
+    print(f"mixed vs FP64 adjoint (budget {budget}): lnZ {dl:.2e}, dbeta {db:.2e}, dh {dh:.2e}")
+    assert dl < 1e-5
+    assert db < 3e-4
+    assert dh < 1e-3
+
+
 def test_backward_matches_central_differences(H):
     beta, h, dcut, n, d = 0.1497, 1e-4, 4, 12, 1e-5
     lnz, db, dh = gpu_grad(H, beta, h, dcut, n)
