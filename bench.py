@@ -55,6 +55,10 @@ def parse():
                    help="run bf16x3 and FP64 flows of NSTEPS steps side by side for each --betas "
                         "and print the per-step differences of lnZ/N, e, m (impurity estimators)")
     p.add_argument("--betas", type=str, default="0.1490,0.1497,0.1502")
+    p.add_argument("--table", type=str, default="", metavar="DCUTS",
+                   help="comma-separated Dcut values: forward step and reverse pass, mixed vs FP64")
+    p.add_argument("--table-precisions", type=str, default="bf16x3,fp64")
+    p.add_argument("--table-parts", type=str, default="forward,adjoint")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of 2 GiB (for scaling HBM byte counters)")
     return p.parse_args()
@@ -160,6 +164,62 @@ def adjoint_run(a):
     }), flush=True)
 
 
+def table_run(a):
+    """Per Dcut and precision: one steady-state forward step with impurities
+    (after the three ramp-up steps), and the reverse pass of a checkpointed
+    pure-T flow of four steps (three ramp-up + one steady-state step).  One
+    JSON line per measurement."""
+    import torch
+    from paper_1906_06060_amd import hotrg as H
+    for D in [int(x) for x in a.table.split(",")]:
+        for pname in a.table_precisions.split(","):
+            prec = H.BF16X3 if pname == "bf16x3" else H.FP64
+            peak = PEAK_BF16 if prec == H.BF16X3 else PEAK_FP64
+            issue = 3.0 if prec == H.BF16X3 else 1.0
+            parts = a.table_parts.split(",")
+            if "forward" in parts:
+                ctx = H.Context(a.beta, a.h, D, precision=prec, impurities=True)
+                for n in range(3):
+                    ctx.step(n % 4)
+                    print(f"[table] Dcut={D} {pname} forward ramp step {n + 1} done", file=sys.stderr, flush=True)
+                dims_in, _ = ctx.dims()
+                ctx.reset_stats()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.step(3)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                ob = ctx.observables()
+                st = ctx.gemm_stats()
+                ctx.close()
+                flops = st["flops"]  # 2 M N K summed over the step's contraction GEMMs
+                print(json.dumps({"table": "forward", "dcut": D, "precision": pname, "step_s": round(dt, 3),
+                                  "step_flops": flops, "dims_in": list(dims_in),
+                                  "tflops_alg": round(flops / dt / 1e12, 2),
+                                  "pct_peak_issued": round(100 * issue * flops / dt / peak, 2),
+                                  "gemm_s": round(st["ms"] / 1e3, 3),
+                                  "device_gb": round(ob["device_bytes"] / 1e9, 2),
+                                  "lnz_per_site": ob["lnz_per_site"], "dims": list(ob["dims"])}), flush=True)
+            if "adjoint" in parts:
+                ctx = H.Context(a.beta, a.h, D, precision=prec, impurities=False, keep_checkpoints=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for n in range(4):
+                    ctx.step(n % 4)
+                    print(f"[table] Dcut={D} {pname} checkpointed step {n + 1} done", file=sys.stderr, flush=True)
+                lnz = ctx.lnz()
+                t1 = time.perf_counter()
+                db, dh = ctx.backward()
+                t2 = time.perf_counter()
+                ob = ctx.observables()
+                ctx.close()
+                print(json.dumps({"table": "adjoint", "dcut": D, "precision": pname, "steps": 4,
+                                  "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+                                  "backward_over_forward": round((t2 - t1) / (t1 - t0), 2),
+                                  "device_gb": round(ob["device_bytes"] / 1e9, 2),
+                                  "lnz_per_site": lnz, "dlnz_dbeta": db, "dlnz_dh": dh}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -178,6 +238,9 @@ def main():
         return
     if a.precision_study:
         precision_study(a)
+        return
+    if a.table:
+        table_run(a)
         return
     from paper_1906_06060_amd import hotrg as H
     prec = H.BF16X3 if a.precision == "bf16x3" else H.FP64
@@ -238,7 +301,7 @@ def main():
             "lnz_per_site": ob["lnz_per_site"], "nn_imp": ob["nn_imp"], "m_imp": ob["m_imp"], "X": ob["X"],
         },
         "roofline": {
-            "bound": "mfma",
+            "bound": "mfma" if prec == H.BF16X3 else "alu",
             "kernel": "gemm_bf16x3_kernel" if prec == H.BF16X3 else "gemm_f64_kernel",
             "achieved": round(achieved / 1e12, 3),
             "peak": peak / 1e12,

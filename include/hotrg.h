@@ -73,7 +73,10 @@ int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotr
  * eigendecomposition on the device, truncation to k <= dcut, then
  * T' = U U U . T . T . U U U contracted on the MFMA cores, and S_m' = U.S_m.T.U,
  * S_e' = U.S_e.S_e.U on the first step and U.S_e.T.U afterwards.  All three
- * are divided by c_n = |T'|_F; ln Z bookkeeping is updated in FP64. */
+ * are divided by c_n = |T'|_F; ln Z bookkeeping is updated in FP64.
+ * With the environment variable HOTRG_PROGRESS=1, long contractions (and
+ * reverse steps of hotrg_backward) print about ten progress lines to stderr,
+ * each after the device has finished the K slices it counts. */
 int hotrg_step(hotrg_ctx *ctx, int axis);
 
 /* ln Z / N after n steps (N = 2^n sites, Eqs. (2.3)-(2.5)):

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <string>
@@ -399,6 +400,27 @@ void canon_strides(const int D[4], uint64_t st[8]) {
     }
 }
 
+// Optional progress report for long steps (environment HOTRG_PROGRESS=1):
+// about ten lines per contraction or reverse step, each printed after the
+// stream has finished the slices it counts.
+bool progress_enabled() {
+    static const bool on = [] {
+        const char *v = std::getenv("HOTRG_PROGRESS");
+        return v && v[0] == '1';
+    }();
+    return on;
+}
+
+int report_progress(hotrg_ctx *c, const char *what, int step, int done, int total) {
+    if (!progress_enabled() || total < 10) return HOTRG_OK;
+    const int every = total / 10;
+    if (done % every != 0 && done != total) return HOTRG_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::fprintf(stderr, "hotrg: step %d %s: %d / %d slices done\n", step, what, done, total);
+    std::fflush(stderr);
+    return HOTRG_OK;
+}
+
 hipEvent_t next_event(hotrg_ctx *c) {
     if (c->ev_used == c->ev_pool.size()) {
         hipEvent_t e;
@@ -639,6 +661,8 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     const uint64_t rs0 = (uint64_t)kb * Dm * kc * ld, rs1 = (uint64_t)Dm * kc * ld, rs2 = (uint64_t)kc * ld;
 
     bool first_slice = true;
+    const int nslices = Dm * Da * (Db / Eb);
+    int sdone = 0;
     for (int g = 0; g < Dm; ++g) {       // alpha
       for (int f = 0; f < Da; ++f) {     // a1'
         for (int e0 = 0; e0 < Db; e0 += Eb) {  // first b1' of the slice
@@ -762,6 +786,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
             }
             first_slice = false;
             TRY(check_launch(c, "contraction slice"));
+            TRY(report_progress(c, "contraction", c->n + 1, ++sdone, nslices));
         }
       }
     }
@@ -957,7 +982,8 @@ int run_einsum(hotrg_ctx *c, EP &e, const double *X, uint64_t xa, const double *
 // A_bar_s = C_bar B_s and B_bar_s = C_bar^T A_s, which flow back through the
 // isometry products into T and the isometries; the isometries flow back
 // through the eigendecomposition and the environments into T.
-int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *Tbar, double *Tprev, bool mixed) {
+int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *Tbar, double *Tprev, bool mixed,
+                  int step) {
     const int *D = cp.dims;
     const int mu = cp.axis;
     const int *tv = cp.tv;
@@ -1072,6 +1098,8 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
     // row-index strides of (a, b, mu1, c) in C / the operands
     const uint64_t r0 = (uint64_t)kb * Dm * kc, r1 = (uint64_t)Dm * kc, r2 = kc;
 
+    const int nslices = Dm * Da * (Db / Eb);
+    int sdone = 0;
     for (int g = 0; g < Dm; ++g) {
       for (int f = 0; f < Da; ++f) {
         for (int e0 = 0; e0 < Db; e0 += Eb) {  // first b1' of the slice
@@ -1340,6 +1368,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 TRY(run_einsum(c, e, T + offB, tsize - offB, Yb1, c->cap, Ubar[0] + (size_t)f * Da * ka,
                                usz[0] - (uint64_t)f * Da * ka, 1.0, 1, "bw Ua_bar (B)"));
             }
+            TRY(report_progress(c, "reverse", step, ++sdone, nslices));
         }
       }
     }
@@ -1424,7 +1453,7 @@ int backward(hotrg_ctx *c, double *dbeta, double *dh) {
     for (int k = c->n - 1; k >= 0; --k) {
         // the precision of step k + 1 in the forward flow
         const bool mixed = c->cfg.precision == HOTRG_BF16X3 && (k + 1) >= c->cfg.mixed_from_step;
-        TRY(backward_step(c, c->ckpts[k], Tb, Tp, mixed));
+        TRY(backward_step(c, c->ckpts[k], Tb, Tp, mixed, k + 1));
         std::swap(Tb, Tp);
     }
     // d T^(0) / d(beta, h): W[0] = (sqrt cosh b, sqrt sinh b), V = e^{+-b h}
