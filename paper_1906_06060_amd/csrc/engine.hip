@@ -125,7 +125,7 @@ struct hotrg_ctx {
     bool ckpt_broken = false;
     double c0 = 1.0;
     // reverse-pass work buffers
-    DevBuf bw[13];
+    DevBuf bw[14];
 };
 
 namespace {
@@ -957,7 +957,8 @@ int read_obs(hotrg_ctx *c, double *tr, double *trm, double *tre, std::vector<dou
 // Work buffers of the reverse pass (grown on demand, kept for later calls).
 enum {
     BW_TBAR0, BW_TBAR1, BW_CBAR, BW_CBART, BW_AT, BW_BT, BW_ABAR, BW_BBAR, BW_Z1, BW_Z2, BW_YB1, BW_YB2,
-    BW_X3  // packed bf16 hi / lo of C_bar, C_bar^T, A^T, B^T (mixed precision)
+    BW_X3,   // packed bf16 hi / lo of C_bar, C_bar^T, A^T, B^T (mixed precision)
+    BW_PART  // per-workgroup isometry-adjoint sums of the fused last-product adjoint
 };
 
 template <typename T>
@@ -974,6 +975,26 @@ int run_einsum(hotrg_ctx *c, EP &e, const double *X, uint64_t xa, const double *
     if (!e.fits(xa, ya, za)) return set_err(HOTRG_EINVAL, std::string(what) + ": launch out of bounds");
     launch_einsum(e.done(alpha, accumulate), X, Y, out, c->gram_part, kPartialCap, c->stream);
     return check_launch(c, what);
+}
+
+// Fused adjoint of the last isometry product (output + isometry adjoint) when
+// the sizes allow it; false -> the caller runs the two generic contractions.
+int run_lastprod(hotrg_ctx *c, const LastProdParams &p, const double *X, uint64_t xa, const double *Y,
+                 const double *U, uint64_t ua, double *out, uint64_t oa, double *Ubar, bool *done) {
+    *done = false;
+    const uint64_t xmax = (uint64_t)(p.n_o1 - 1) * p.x_o1 + (uint64_t)(p.n_o2 - 1) * p.x_o2 +
+                          (uint64_t)(p.NJ - 1) * p.xj + (uint64_t)(p.L - 1) * p.xc + (uint64_t)(p.N - 1) * p.xs;
+    const uint64_t omax = (uint64_t)(p.n_o1 - 1) * p.out_o1 + (uint64_t)(p.n_o2 - 1) * p.out_o2 +
+                          (uint64_t)(p.NJ - 1) * p.oj + (uint64_t)(p.N - 1) * p.ol;
+    const uint64_t umax = (uint64_t)(p.N - 1) * (p.ul + p.us) + (uint64_t)(p.L - 1) * p.uc;
+    if (p.n_o1 == 0 || p.n_o2 == 0 || p.NJ == 0 || xmax >= xa || omax >= oa || umax >= ua || xmax >= (1ull << 32) ||
+        omax >= (1ull << 32))
+        return HOTRG_OK;
+    double *part;
+    TRY(bw_buf(c, BW_PART, (size_t)p.n_o1 * p.n_o2 * p.L * p.N * p.N, &part));
+    if (!launch_lastprod_adjoint(p, X, Y, U, out, Ubar, part, c->stream)) return HOTRG_OK;
+    *done = true;
+    return check_launch(c, "last-product adjoint");
 }
 
 // Tbar_prev (dims of the checkpoint) = adjoint of one step applied to Tbar
@@ -1133,14 +1154,15 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 launch_iso_expand(x.done(), Y1, Ub, Y2, nullptr, nullptr, c->stream);
             }
             {
-                XP x;  // P3 -> A^T [K][M] (row length ldM)
-                x.tdim(ka, y2s[0], r0);
-                x.tdim(kb, y2s[1], r1);
-                x.tdim(Dm, y2s[2], r2);
+                XP x;  // P3 -> A^T [K][M] (row length ldM); the GEMM-row dims innermost, so that
+                       // neighbouring lanes write neighbouring columns of A^T
                 x.tdim(Eb, y2s[3], ks0 * ldM);
                 x.tdim(Dc, y2s[4], ks1 * ldM);
                 x.tdim(Da, y2s[5], ks2 * ldM);
                 x.tdim(Db, y2s[6], ks3 * ldM);
+                x.tdim(ka, y2s[0], r0);
+                x.tdim(kb, y2s[1], r1);
+                x.tdim(Dm, y2s[2], r2);
                 x.loops(kc, 1, 1, Dc, kc, ldM);
                 x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
                 if (!x.fits(c->cap, usz[2], ldM * Ks)) return set_err(HOTRG_EINVAL, "bw P3 out of bounds");
@@ -1179,14 +1201,14 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 launch_iso_expand(x.done(), Z1, Ub + uboff, Z2, nullptr, nullptr, c->stream);
             }
             {
-                XP x;  // Q3 -> B^T [K][N] (row length ldM)
-                x.tdim(ka, z2s[0], r0);
-                x.tdim(kb, z2s[1], r1);
-                x.tdim(Dm, z2s[2], r2);
+                XP x;  // Q3 -> B^T [K][N] (row length ldM); GEMM-row dims innermost as in P3
                 x.tdim(Eb, z2s[3], ks0 * ldM);
                 x.tdim(Da, z2s[4], ks2 * ldM);
                 x.tdim(Db, z2s[5], ks3 * ldM);
                 x.tdim(Dc, z2s[6], ldM);
+                x.tdim(ka, z2s[0], r0);
+                x.tdim(kb, z2s[1], r1);
+                x.tdim(Dm, z2s[2], r2);
                 x.loops(kc, 1, 1, Dc, (uint64_t)Dc * kc, ks1 * ldM);
                 x.sum(Dc, z2s[7], kc);
                 if (!x.fits(c->cap, usz[2], ldM * Ks)) return set_err(HOTRG_EINVAL, "bw Q3 out of bounds");
@@ -1208,7 +1230,27 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
             TRY(check_launch(c, "reverse GEMMs"));
 
             // ---- A side: through P3, P2, P1
-            {   // Yb2[a,b,mu1,b1',c1',a2,b2,c1] = sum_{c,c2} Uc[(c1,c2),c] A_bar[(a,b,mu1,c),(b1',c1',a2,b2,c2)]
+            bool fusedA = false;
+            {   // Yb2 and Uc_bar (A) in one pass over A_bar (rows (a,b,mu1 | c), columns (K' | c2))
+                LastProdParams lp{};
+                lp.n_o1 = (uint32_t)((uint64_t)ka * kb * Dm);
+                lp.n_o2 = 1;
+                lp.NJ = (uint32_t)((uint64_t)Eb * Dc * Da * Db);
+                lp.x_o1 = (uint32_t)(kc * Ks);
+                lp.xj = Dc;
+                lp.xc = (uint32_t)Ks;
+                lp.xs = 1;
+                lp.out_o1 = (uint32_t)y2s[2];
+                lp.oj = (uint32_t)y2s[6];
+                lp.ol = (uint32_t)y2s[7];
+                lp.ul = (uint32_t)((uint64_t)Dc * kc);
+                lp.us = (uint32_t)kc;
+                lp.uc = 1;
+                lp.L = kc;
+                lp.N = Dc;
+                TRY(run_lastprod(c, lp, Abar, M * Ks, Y2, Uc, usz[2], Yb2, c->cap, Ubar[2], &fusedA));
+            }
+            if (!fusedA) {   // Yb2[a,b,mu1,b1',c1',a2,b2,c1] = sum_{c,c2} Uc[(c1,c2),c] A_bar[(a,b,mu1,c),(b1',c1',a2,b2,c2)]
                 EP e;
                 e.o(ka, r0 * Ks, 0, y2s[0]);
                 e.o(kb, r1 * Ks, 0, y2s[1]);
@@ -1222,7 +1264,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.s(Dc, 1, kc);
                 TRY(run_einsum(c, e, Abar, M * Ks, Uc, usz[2], Yb2, c->cap, 1.0, 0, "bw Y2bar"));
             }
-            {   // Uc_bar[(c1,c2),c] += sum Y2[.., c1] A_bar[(.., c), (.., c2)]
+            if (!fusedA) {   // Uc_bar[(c1,c2),c] += sum Y2[.., c1] A_bar[(.., c), (.., c2)]
                 EP e;
                 e.o(Dc, y2s[7], 0, (uint64_t)Dc * kc);
                 e.o(Dc, 0, 1, kc);
@@ -1287,7 +1329,30 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 TRY(run_einsum(c, e, T + offA, tsize - offA, Yb1, c->cap, Ubar[0], usz[0], 1.0, 1, "bw Ua_bar (A)"));
             }
             // ---- B side: through Q3, Q2, Q1
-            {   // Zb2[a',b',mu2',b1',a2,b2,c2,c2'] = sum_{c',c1'} Uc[(c1',c2'),c'] B_bar[(a',b',mu2',c'),(b1',c1',a2,b2,c2)]
+            bool fusedB = false;
+            {   // Zb2 and Uc_bar (B) in one pass over B_bar (rows (a',b',mu2' | c'), columns
+                // (b1' | c1' | a2,b2,c2))
+                LastProdParams lp{};
+                lp.n_o1 = (uint32_t)((uint64_t)ka * kb * Dm);
+                lp.n_o2 = (uint32_t)Eb;
+                lp.NJ = (uint32_t)((uint64_t)Da * Db * Dc);
+                lp.x_o1 = (uint32_t)(kc * Ks);
+                lp.x_o2 = (uint32_t)ks0;
+                lp.xj = 1;
+                lp.xc = (uint32_t)Ks;
+                lp.xs = (uint32_t)ks1;
+                lp.out_o1 = (uint32_t)z2s[2];
+                lp.out_o2 = (uint32_t)z2s[3];
+                lp.oj = (uint32_t)z2s[6];
+                lp.ol = (uint32_t)z2s[7];
+                lp.ul = (uint32_t)kc;
+                lp.us = (uint32_t)((uint64_t)Dc * kc);
+                lp.uc = 1;
+                lp.L = kc;
+                lp.N = Dc;
+                TRY(run_lastprod(c, lp, Bbar, M * Ks, Z2, Uc, usz[2], Yb2, c->cap, Ubar[2], &fusedB));
+            }
+            if (!fusedB) {   // Zb2[a',b',mu2',b1',a2,b2,c2,c2'] = sum_{c',c1'} Uc[(c1',c2'),c'] B_bar[(a',b',mu2',c'),(b1',c1',a2,b2,c2)]
                 EP e;
                 e.o(ka, r0 * Ks, 0, z2s[0]);
                 e.o(kb, r1 * Ks, 0, z2s[1]);
@@ -1301,7 +1366,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 e.s(Dc, ks1, (uint64_t)Dc * kc);
                 TRY(run_einsum(c, e, Bbar, M * Ks, Uc, usz[2], Yb2, c->cap, 1.0, 0, "bw Z2bar"));
             }
-            {   // Uc_bar[(c1',c2'),c'] += sum Z2[.., c2'] B_bar[(.., c'), (b1', c1', ..)]
+            if (!fusedB) {   // Uc_bar[(c1',c2'),c'] += sum Z2[.., c2'] B_bar[(.., c'), (b1', c1', ..)]
                 EP e;
                 e.o(Dc, 0, ks1, (uint64_t)Dc * kc);
                 e.o(Dc, z2s[7], 0, kc);

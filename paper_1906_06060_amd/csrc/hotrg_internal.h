@@ -105,6 +105,21 @@ struct EinsumParams {
     int accumulate;
 };
 
+// Adjoint of the last isometry product of one K slice, fused with the
+// adjoint of that isometry (one pass over the operand adjoint X):
+//   out[o, j, l]    = sum_{c, s} U[l, s, c] X[o, j, c, s]
+//   Ubar[l, s, c] += sum_{o, j} Y[o, j, l] X[o, j, c, s]
+// with o = (o1, o2), offsets  X: o1 x_o1 + o2 x_o2 + j xj + c xc + s xs,
+// out / Y: o1 out_o1 + o2 out_o2 + j oj + l ol,  U / Ubar: l ul + s us + c uc;
+// c < L, s, l < N.  Element offsets below 2^32.
+struct LastProdParams {
+    uint32_t n_o1, n_o2, NJ;
+    uint32_t x_o1, x_o2, xj, xc, xs;
+    uint32_t out_o1, out_o2, oj, ol;
+    uint32_t ul, us, uc;
+    int L, N;
+};
+
 constexpr int PERM_MAXD = 8;
 struct PermParams {
     int nd;
@@ -151,6 +166,11 @@ void launch_split_pack(const double *X, uint32_t R, uint32_t K, uint32_t ld, uin
                        hipStream_t s);
 
 // reverse pass (kernels_adjoint.hip)
+// LastProdParams contraction; partial: n_o1 * n_o2 * L * N * N doubles of
+// per-workgroup sums, added into Ubar in a fixed order.  Returns false (and
+// launches nothing) if N is not one of the compiled sizes (2 .. 12) or L > 16.
+bool launch_lastprod_adjoint(const LastProdParams &p, const double *X, const double *Y, const double *U,
+                             double *out, double *Ubar, double *partial, hipStream_t s);
 void launch_einsum(EinsumParams p, const double *X, const double *Y, double *out, double *partial,
                    size_t partial_cap, hipStream_t s);
 void launch_eigh_adjoint(const double *V, const double *lam, const double *Ubar, int n, int k, double *Ebar,

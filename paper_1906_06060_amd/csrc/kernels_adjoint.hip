@@ -109,6 +109,127 @@ void launch_einsum(EinsumParams p, const double *X, const double *Y, double *out
 }
 
 // ---------------------------------------------------------------------------
+// Fused adjoint of the last isometry product of a K slice (see
+// LastProdParams).  Workgroup (o1, o2) walks j in tiles of JT: the tile of X
+// (JT x L x N) and of Y (JT x N) is staged in LDS, the JT x N outputs are
+// written (sum over c, then s, in the order of the generic contraction), and
+// each thread keeps running sums of its isometry-adjoint entries; at the end
+// the workgroup stores them as one row of `partial`.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int LP_JT = 32;
+constexpr int LP_MAXL = 16;
+constexpr int LP_UPT = 9;  // isometry-adjoint entries per thread: L N N <= 16 * 12 * 12 = 2304 = 256 * 9
+}  // namespace
+
+template <int N>
+__global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, const double *__restrict__ X,
+                                                              const double *__restrict__ Y,
+                                                              const double *__restrict__ U,
+                                                              double *__restrict__ out,
+                                                              double *__restrict__ partial) {
+    extern __shared__ double lp_sm[];
+    const int L = p.L;
+    double *sU = lp_sm;                       // [l][s][c]  N * N * L
+    double *sX = sU + N * N * L;              // [jj][c][s] JT * L * N
+    double *sY = sX + LP_JT * L * N;          // [jj][l]    JT * N
+    const int tid = threadIdx.x;
+    const int nU = N * N * L;
+    for (int u = tid; u < nU; u += blockDim.x) {
+        const int c = u % L, s = (u / L) % N, l = u / (L * N);
+        sU[u] = U[l * p.ul + s * p.us + c * p.uc];
+    }
+    const uint32_t o1 = blockIdx.x / p.n_o2, o2 = blockIdx.x % p.n_o2;
+    const uint32_t xo = o1 * p.x_o1 + o2 * p.x_o2, oo = o1 * p.out_o1 + o2 * p.out_o2;
+    double pacc[LP_UPT];
+#pragma unroll
+    for (int q = 0; q < LP_UPT; ++q) pacc[q] = 0.0;
+    for (uint32_t j0 = 0; j0 < p.NJ; j0 += LP_JT) {
+        __syncthreads();  // previous tile consumed (and sU staged on the first pass)
+        for (int idx = tid; idx < LP_JT * L * N; idx += blockDim.x) {
+            const int s = idx % N, c = (idx / N) % L, jj = idx / (N * L);
+            const uint32_t j = j0 + jj;
+            sX[idx] = j < p.NJ ? X[xo + j * p.xj + c * p.xc + s * p.xs] : 0.0;
+        }
+        for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
+            const int l = idx % N, jj = idx / N;
+            const uint32_t j = j0 + jj;
+            sY[idx] = j < p.NJ ? Y[oo + j * p.oj + l * p.ol] : 0.0;
+        }
+        __syncthreads();
+        // outputs of the tile
+        for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
+            const int l = idx % N, jj = idx / N;
+            const uint32_t j = j0 + jj;
+            if (j >= p.NJ) continue;
+            const double *xr = sX + jj * L * N;
+            const double *ur = sU + l * N * L;
+            double acc = 0.0;
+            for (int c = 0; c < L; ++c)
+#pragma unroll
+                for (int s = 0; s < N; ++s) acc = fma(ur[s * L + c], xr[c * N + s], acc);
+            out[oo + j * p.oj + l * p.ol] = acc;
+        }
+        // isometry-adjoint running sums (padding rows of the tile are zero)
+#pragma unroll
+        for (int q = 0; q < LP_UPT; ++q) {
+            const int u = tid + q * (int)blockDim.x;
+            if (u >= nU) break;
+            const int c = u % L, s = (u / L) % N, l = u / (L * N);
+            double a = pacc[q];
+#pragma unroll 4
+            for (int jj = 0; jj < LP_JT; ++jj) a = fma(sY[jj * N + l], sX[(jj * L + c) * N + s], a);
+            pacc[q] = a;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < LP_UPT; ++q) {
+        const int u = tid + q * (int)blockDim.x;
+        if (u < nU) partial[(size_t)blockIdx.x * nU + u] = pacc[q];
+    }
+}
+
+__global__ void __launch_bounds__(kT) lastprod_reduce_kernel(LastProdParams p, const double *__restrict__ partial,
+                                                             uint32_t nblocks, double *__restrict__ Ubar) {
+    const int L = p.L, N = p.N, nU = N * N * L;
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nU; u += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (uint32_t b = 0; b < nblocks; ++b) acc += partial[(size_t)b * nU + u];
+        const int c = u % L, s = (u / L) % N, l = u / (L * N);
+        Ubar[l * p.ul + s * p.us + c * p.uc] += acc;
+    }
+}
+
+template <int N>
+void launch_lastprod_n(const LastProdParams &p, const double *X, const double *Y, const double *U, double *out,
+                       double *Ubar, double *partial, hipStream_t s) {
+    const uint32_t nb = p.n_o1 * p.n_o2;
+    const size_t lds = sizeof(double) * ((size_t)N * N * p.L + (size_t)LP_JT * p.L * N + (size_t)LP_JT * N);
+    lastprod_adjoint_kernel<N><<<nb, kT, lds, s>>>(p, X, Y, U, out, partial);
+    const int nU = N * N * p.L;
+    lastprod_reduce_kernel<<<(nU + kT - 1) / kT, kT, 0, s>>>(p, partial, nb, Ubar);
+}
+
+bool launch_lastprod_adjoint(const LastProdParams &p, const double *X, const double *Y, const double *U,
+                             double *out, double *Ubar, double *partial, hipStream_t s) {
+    if (p.L < 1 || p.L > LP_MAXL || p.N * p.N * p.L > kT * LP_UPT || p.n_o1 * p.n_o2 == 0) return false;
+    switch (p.N) {
+        case 2: launch_lastprod_n<2>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 3: launch_lastprod_n<3>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 4: launch_lastprod_n<4>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 5: launch_lastprod_n<5>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 6: launch_lastprod_n<6>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 7: launch_lastprod_n<7>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 8: launch_lastprod_n<8>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 9: launch_lastprod_n<9>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 10: launch_lastprod_n<10>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 11: launch_lastprod_n<11>(p, X, Y, U, out, Ubar, partial, s); return true;
+        case 12: launch_lastprod_n<12>(p, X, Y, U, out, Ubar, partial, s); return true;
+        default: return false;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint of the truncated eigenvectors.  V: n x n row-major, column j is the
 // j-th eigenvector (descending lam); U = V[:, :k]; Ubar: n x k row-major.
 // ---------------------------------------------------------------------------
