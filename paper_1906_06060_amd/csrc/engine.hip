@@ -991,7 +991,7 @@ int run_lastprod(hotrg_ctx *c, const LastProdParams &p, const double *X, uint64_
         omax >= (1ull << 32))
         return HOTRG_OK;
     double *part;
-    TRY(bw_buf(c, BW_PART, (size_t)p.n_o1 * p.n_o2 * p.L * p.N * p.N, &part));
+    TRY(bw_buf(c, BW_PART, ((size_t)p.n_o1 * p.n_o2 + 64) * p.L * p.N * p.N, &part));
     if (!launch_lastprod_adjoint(p, X, Y, U, out, Ubar, part, c->stream)) return HOTRG_OK;
     *done = true;
     return check_launch(c, "last-product adjoint");

@@ -166,8 +166,8 @@ void launch_split_pack(const double *X, uint32_t R, uint32_t K, uint32_t ld, uin
                        hipStream_t s);
 
 // reverse pass (kernels_adjoint.hip)
-// LastProdParams contraction; partial: n_o1 * n_o2 * L * N * N doubles of
-// per-workgroup sums, added into Ubar in a fixed order.  Returns false (and
+// LastProdParams contraction; partial: (n_o1 * n_o2 + 64) * L * N * N doubles
+// (per-workgroup sums, then 64 group sums), added into Ubar in a fixed order.  Returns false (and
 // launches nothing) if N is not one of the compiled sizes (2 .. 12) or L > 16.
 bool launch_lastprod_adjoint(const LastProdParams &p, const double *X, const double *Y, const double *U,
                              double *out, double *Ubar, double *partial, hipStream_t s);

@@ -189,12 +189,26 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
     }
 }
 
-__global__ void __launch_bounds__(kT) lastprod_reduce_kernel(LastProdParams p, const double *__restrict__ partial,
-                                                             uint32_t nblocks, double *__restrict__ Ubar) {
+// Fixed-order reduction of the per-workgroup rows in two passes: group g of
+// LP_G sums rows g, g + LP_G, ... into part2[g]; then part2 is summed in
+// order and added into Ubar.
+constexpr int LP_G = 64;
+__global__ void __launch_bounds__(kT) lastprod_reduce1_kernel(const double *__restrict__ partial, uint32_t nblocks,
+                                                              int nU, double *__restrict__ part2) {
+    const int g = blockIdx.y;
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nU; u += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (uint32_t b = g; b < nblocks; b += LP_G) acc += partial[(size_t)b * nU + u];
+        part2[(size_t)g * nU + u] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(kT) lastprod_reduce2_kernel(LastProdParams p, const double *__restrict__ part2,
+                                                              double *__restrict__ Ubar) {
     const int L = p.L, N = p.N, nU = N * N * L;
     for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nU; u += gridDim.x * blockDim.x) {
         double acc = 0.0;
-        for (uint32_t b = 0; b < nblocks; ++b) acc += partial[(size_t)b * nU + u];
+        for (int g = 0; g < LP_G; ++g) acc += part2[(size_t)g * nU + u];
         const int c = u % L, s = (u / L) % N, l = u / (L * N);
         Ubar[l * p.ul + s * p.us + c * p.uc] += acc;
     }
@@ -207,7 +221,10 @@ void launch_lastprod_n(const LastProdParams &p, const double *X, const double *Y
     const size_t lds = sizeof(double) * ((size_t)N * N * p.L + (size_t)LP_JT * p.L * N + (size_t)LP_JT * N);
     lastprod_adjoint_kernel<N><<<nb, kT, lds, s>>>(p, X, Y, U, out, partial);
     const int nU = N * N * p.L;
-    lastprod_reduce_kernel<<<(nU + kT - 1) / kT, kT, 0, s>>>(p, partial, nb, Ubar);
+    double *part2 = partial + (size_t)nb * nU;  // LP_G rows after the per-workgroup ones
+    const int gx = (nU + kT - 1) / kT;
+    lastprod_reduce1_kernel<<<dim3(gx, LP_G), kT, 0, s>>>(partial, nb, nU, part2);
+    lastprod_reduce2_kernel<<<gx, kT, 0, s>>>(p, part2, Ubar);
 }
 
 bool launch_lastprod_adjoint(const LastProdParams &p, const double *X, const double *Y, const double *U,
