@@ -12,7 +12,7 @@
 //                  256 x 256 tile, 8 waves of 128 x 64 (two per SIMD), 32 k
 //                  per LDS stage loaded directly into a two-slot LDS ring
 //                  (operands in a packed, stage-contiguous layout), FP32
-//                  accumulation inside chunks of 8192 k; each chunk is added
+//                  accumulation inside chunks of 32768 k; each chunk is added
 //                  into the FP64 output tile (owned by one workgroup, so no
 //                  atomics).
 // Tiles are ordered so that the blocks an XCD runs together form a compact
@@ -128,7 +128,7 @@ namespace x3 {
 constexpr int BM = 256, BN = 256;
 constexpr int BK = PACK_K;   // k per LDS stage: one packed block of every operand
 constexpr int NT = 512;      // eight waves, two per SIMD, each 128 x 64 of the tile
-constexpr int KC = 8192;     // k per FP32 accumulation chunk
+constexpr int KC = 32768;    // k per FP32 accumulation chunk (each flush read-modify-writes the FP64 tile)
 constexpr size_t OPB = (size_t)BM * BK * sizeof(uint16_t);  // one operand block: 16 KB
 constexpr size_t STAGE = 4 * OPB;                            // Ah, Al, Bh, Bl: 64 KB
 constexpr size_t LDS_FLUSH = (size_t)8 * 32 * 65 * sizeof(float);

@@ -190,7 +190,7 @@ void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, 
                      size_t ldb, size_t ldc, int accumulate, hipStream_t s);
 // Same product from bf16 hi/lo splits: A ~ Ah + Al, B ~ Bh + Bl; computes
 // Ah Bh^T + Ah Bl^T + Al Bh^T with FP32 MFMA accumulation over chunks of at
-// most 8192 k, summed in FP64.  Operands are in the packed layout below; A
+// most 32768 k, summed in FP64.  Operands are in the packed layout below; A
 // stacks ntA tensors of M rows each (C rows t M + r), B has N rows; K is a
 // multiple of 64.
 //
