@@ -59,6 +59,13 @@ def parse():
                    help="comma-separated Dcut values: forward step and reverse pass, mixed vs FP64")
     p.add_argument("--table-precisions", type=str, default="bf16x3,fp64")
     p.add_argument("--table-parts", type=str, default="forward,adjoint")
+    p.add_argument("--tc", type=str, default="", metavar="DCUTS",
+                   help="comma-separated Dcut values: locate T_c(Dcut) from the settled X indicator "
+                        "(scan --tc-scan for a bracket, then --tc-iterations bisection rounds)")
+    p.add_argument("--tc-scan", type=str, default="0.144:0.156:0.002", metavar="LO:HI:STEP")
+    p.add_argument("--tc-iterations", type=int, default=10)
+    p.add_argument("--tc-steps", type=int, default=40)
+    p.add_argument("--tc-precision", choices=["bf16x3", "fp64"], default="bf16x3")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of 2 GiB (for scaling HBM byte counters)")
     return p.parse_args()
@@ -164,6 +171,46 @@ def adjoint_run(a):
     }), flush=True)
 
 
+def tc_run(a):
+    """T_c(Dcut) from X^(n) (Sec. 3): per Dcut, pure-T flows at h = 0 over a
+    beta grid until the settled X changes from 1 to 2, then bisection."""
+    from paper_1906_06060_amd import hotrg as H
+    from paper_1906_06060_amd import tc
+    prec = H.BF16X3 if a.tc_precision == "bf16x3" else H.FP64
+    lo, hi, st = (float(v) for v in a.tc_scan.split(":"))
+    grid = [round(lo + i * st, 10) for i in range(int(round((hi - lo) / st)) + 1)]
+    for dcut in [int(v) for v in a.tc.split(",")]:
+        cache, times = {}, []
+
+        def x_of(beta):
+            if beta not in cache:
+                t0 = time.perf_counter()
+                cache[beta] = tc.x_history(beta, dcut, a.tc_steps, prec)[-1]
+                times.append(time.perf_counter() - t0)
+                print(f"[tc] Dcut={dcut} beta={beta:.9f} X={cache[beta]:.6f} ({times[-1]:.2f} s)",
+                      file=sys.stderr, flush=True)
+            return cache[beta]
+
+        t0 = time.perf_counter()
+        pair, scan = tc.bracket_by_scan(x_of, grid)
+        line = {"metric": "T_c(Dcut) from the settled X indicator", "unit": "T (J = k_B = 1)",
+                "higher_is_better": None,
+                "config": {"workload": f"4D Ising HOTRG, pure T, h = 0, Dcut={dcut}, {a.tc_steps} steps "
+                                       f"(lattice {2 ** (a.tc_steps // 4)}^4), {a.tc_precision}",
+                           "scan": a.tc_scan, "iterations": a.tc_iterations},
+                "scan": [{"beta": p["beta"], "X": p["X"]} for p in scan]}
+        if pair is None:
+            line.update(value=None, error="no disordered-to-ordered change on the scan grid")
+        else:
+            r = tc.bisect_transition(x_of, pair[0], pair[1], a.tc_iterations)
+            line.update(value=r["T_c"], T_c_halfwidth=r["T_c_halfwidth"], beta_c=r["beta_c"],
+                        beta_bracket=[r["beta_lo"], r["beta_hi"]], unsettled_points=r["unsettled"],
+                        bisection=[{"beta": p["beta"], "X": p["X"]} for p in r["points"][2:]])
+        line.update(flows=len(times), seconds_per_flow=round(sum(times) / max(len(times), 1), 3),
+                    total_s=round(time.perf_counter() - t0, 2))
+        print(json.dumps(line), flush=True)
+
+
 def table_run(a):
     """Per Dcut and precision: one steady-state forward step with impurities
     (after the three ramp-up steps), and the reverse pass of a checkpointed
@@ -241,6 +288,9 @@ def main():
         return
     if a.table:
         table_run(a)
+        return
+    if a.tc:
+        tc_run(a)
         return
     from paper_1906_06060_amd import hotrg as H
     prec = H.BF16X3 if a.precision == "bf16x3" else H.FP64

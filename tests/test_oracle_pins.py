@@ -298,3 +298,26 @@ def test_site_tensor_tangent_matches_differences():
         Tp, _ = H.site_tensors(0.2 + (e if wrt == "beta" else 0), 0.3 + (e if wrt == "h" else 0), 4)
         Tm, _ = H.site_tensors(0.2 - (e if wrt == "beta" else 0), 0.3 - (e if wrt == "h" else 0), 4)
         np.testing.assert_allclose(dT, (Tp - Tm) / (2 * e), rtol=1e-7, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# T_c(Dcut) from the X indicator (Sec. 3): the d = 2 flow pins the bisection
+# to Onsager's exact critical coupling; deep in each phase X takes its limit.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("beta,limit", [(0.30, 1.0), (0.60, 2.0)])
+def test_x_indicator_limits_in_each_phase(beta, limit):
+    from oracle import tc
+    assert tc.final_x(beta, 8, 2, 30) == pytest.approx(limit, abs=1e-3)
+
+
+def test_d2_x_bisection_brackets_onsager_beta_c():
+    from oracle import tc
+    beta_c = 0.5 * math.log(1.0 + math.sqrt(2.0))
+    r = tc.bisect(8, 2, 0.40, 0.48, 14, 40)
+    assert r["beta_hi"] - r["beta_lo"] == pytest.approx(0.08 / 2 ** 14)
+    mid = 0.5 * (r["beta_lo"] + r["beta_hi"])
+    assert abs(mid - beta_c) / beta_c < 5e-4
+    # every point on the ordered side of the final bracket has X near 2, on
+    # the disordered side X below the threshold
+    for b, x in r["points"]:
+        assert (x > 1.5) == (b >= r["beta_hi"])
