@@ -372,9 +372,136 @@ void launch_iso_expand_lds(const ExpandParams &p, const double *in, const double
     }
 }
 
+// bf16 hi/lo outputs written as 4-byte (hi, hi') / (lo, lo') pairs of adjacent
+// outputs, laid out so that consecutive lanes write consecutive pairs.
+// PAIR_RUN (the l2 loop is an output run, o2 == 1): unit u = t * N/2 + m
+//   computes outputs (l1, 2m) and (l1, 2m + 1) of multi-index t for every l1;
+//   U is staged as [l1][i][l2] so that one 16-byte LDS read feeds both.
+// PAIR_INNER (otherwise): unit u computes multi-indices t = 2u and 2u + 1,
+//   which differ in the innermost multi-index dim (output stride 1); every U
+//   entry read from LDS feeds two FMAs.
+// The host checks that every pair starts at an even offset and stays inside
+// one packed 32-k piece (iso_pairs_ok).
+template <bool PAIR_RUN, int N>
+__global__ void __launch_bounds__(kThreads) iso_expand_pairs_kernel(ExpandParams p, const double *__restrict__ in,
+                                                                    const double *__restrict__ U,
+                                                                    uint16_t *__restrict__ hi,
+                                                                    uint16_t *__restrict__ lo) {
+    extern __shared__ __align__(16) double sUp[];
+    const int nU = p.L1 * N * N;
+    for (int idx = threadIdx.x; idx < nU; idx += blockDim.x) {
+        const int c = idx % N, b = (idx / N) % N, l1 = idx / (N * N);
+        // PAIR_RUN: [l1][i = b][l2 = c]; PAIR_INNER: [l1][l2 = b][i = c]
+        sUp[idx] = PAIR_RUN ? U[l1 * p.u1 + c * p.u2 + b * p.us] : U[l1 * p.u1 + b * p.u2 + c * p.us];
+    }
+    __syncthreads();
+    constexpr uint32_t NP = N / 2;
+    const uint32_t units = PAIR_RUN ? p.threads * NP : p.threads / 2;
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < units; u += gridDim.x * blockDim.x) {
+        const uint32_t t = PAIR_RUN ? u / NP : 2 * u;
+        const uint32_t m2 = PAIR_RUN ? 2 * (u - t * NP) : 0;
+        uint32_t rem = t, ib = 0, ob = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.ext[k]);
+            uint32_t c = rem - q * p.ext[k].d;
+            ib += c * p.in_st[k];
+            ob += c * p.out_st[k];
+            rem = q;
+        }
+        if (PAIR_RUN) {
+            double v[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = in[ib + i * p.xs];
+#pragma unroll 1
+            for (int l1 = 0; l1 < p.L1; ++l1) {
+                const double *ul = sUp + l1 * N * N + m2;
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const double2 w = *(const double2 *)(ul + i * N);
+                    a0 = fma(w.x, v[i], a0);
+                    a1 = fma(w.y, v[i], a1);
+                }
+                const uint16_t h0 = bf16_bits((float)a0), w0 = bf16_bits((float)(a0 - bf16_value(h0)));
+                const uint16_t h1 = bf16_bits((float)a1), w1 = bf16_bits((float)(a1 - bf16_value(h1)));
+                const size_t q0 = split_offset(p, ob + l1 * p.o1 + m2);
+                *(uint32_t *)(hi + q0) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                *(uint32_t *)(lo + q0) = (uint32_t)w0 | ((uint32_t)w1 << 16);
+            }
+        } else {
+            const uint32_t ib1 = ib + p.in_st[p.nd - 1];
+            double v0[N], v1[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                v0[i] = in[ib + i * p.xs];
+                v1[i] = in[ib1 + i * p.xs];
+            }
+#pragma unroll 1
+            for (int l1 = 0; l1 < p.L1; ++l1) {
+#pragma unroll 1
+                for (int l2 = 0; l2 < N; ++l2) {
+                    const double *ul = sUp + (l1 * N + l2) * N;
+                    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) {
+                        a0 = fma(ul[i], v0[i], a0);
+                        a1 = fma(ul[i], v1[i], a1);
+                    }
+                    const uint16_t h0 = bf16_bits((float)a0), w0 = bf16_bits((float)(a0 - bf16_value(h0)));
+                    const uint16_t h1 = bf16_bits((float)a1), w1 = bf16_bits((float)(a1 - bf16_value(h1)));
+                    const size_t q0 = split_offset(p, ob + l1 * p.o1 + l2 * p.o2);
+                    *(uint32_t *)(hi + q0) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                    *(uint32_t *)(lo + q0) = (uint32_t)w0 | ((uint32_t)w1 << 16);
+                }
+            }
+        }
+    }
+}
+
+// Whether the paired kernel applies: every pair's first offset is even (so the
+// pair is one aligned 4-byte word of one row, and, in the packed layout, of one
+// 32-k piece), and the unit count fits 32 bits.
+bool iso_pairs_ok(const ExpandParams &p, bool run) {
+    if (p.nsum != p.L2 || p.L2 % 2 != 0 || p.L2 > 12 || p.nd < 1) return false;
+    if ((size_t)p.L1 * p.L2 * p.L2 * sizeof(double) > 48 * 1024) return false;
+    if (p.pack && p.pld.d % 2 != 0) return false;
+    if (p.L1 > 1 && p.o1 % 2 != 0) return false;
+    if (run) {
+        for (int k = 0; k < p.nd; ++k)
+            if (p.out_st[k] % 2 != 0) return false;
+        return (uint64_t)p.threads * (p.L2 / 2) < (1ull << 32);
+    }
+    if (p.o2 % 2 != 0 || p.out_st[p.nd - 1] != 1 || p.ext[p.nd - 1].d % 2 != 0) return false;
+    for (int k = 0; k < p.nd - 1; ++k)
+        if (p.out_st[k] % 2 != 0) return false;
+    return true;
+}
+
+template <int N>
+void launch_iso_expand_pairs(const ExpandParams &p, bool run, const double *in, const double *U, uint16_t *hi,
+                             uint16_t *lo, hipStream_t s) {
+    const size_t lds = (size_t)p.L1 * N * N * sizeof(double);
+    const uint64_t units = run ? (uint64_t)p.threads * (N / 2) : p.threads / 2;
+    const int g = grid_for(units, kThreads, 4096);
+    if (run) iso_expand_pairs_kernel<true, N><<<g, kThreads, lds, s>>>(p, in, U, hi, lo);
+    else iso_expand_pairs_kernel<false, N><<<g, kThreads, lds, s>>>(p, in, U, hi, lo);
+}
+
 void launch_iso_expand(const ExpandParams &p, const double *in, const double *U, double *out, uint16_t *hi,
                        uint16_t *lo, hipStream_t s) {
     if (p.threads == 0) return;
+    if (hi && ((uintptr_t)hi & 3) == 0 && ((uintptr_t)lo & 3) == 0 && iso_pairs_ok(p, p.o2 == 1)) {
+        const bool run = p.o2 == 1;
+        switch (p.L2) {
+            case 2: return launch_iso_expand_pairs<2>(p, run, in, U, hi, lo, s);
+            case 4: return launch_iso_expand_pairs<4>(p, run, in, U, hi, lo, s);
+            case 6: return launch_iso_expand_pairs<6>(p, run, in, U, hi, lo, s);
+            case 8: return launch_iso_expand_pairs<8>(p, run, in, U, hi, lo, s);
+            case 10: return launch_iso_expand_pairs<10>(p, run, in, U, hi, lo, s);
+            case 12: return launch_iso_expand_pairs<12>(p, run, in, U, hi, lo, s);
+            default: break;
+        }
+    }
     if (p.nsum == p.L2 && (size_t)p.L1 * p.L2 * p.L2 * sizeof(double) <= 48 * 1024) {
         switch (p.L2) {
             case 2: return launch_iso_expand_lds<2>(p, in, U, out, hi, lo, s);
