@@ -26,7 +26,7 @@ PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
 # HBM bytes per dispatch of the bf16x3 GEMM at this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # plain 2 GiB copy); valid only while the kernel source is the one profiled.
-GEMM_TRAFFIC_BYTES = 326122901403
+GEMM_TRAFFIC_BYTES = 325945601482
 GEMM_TRAFFIC_SRC_SHA = "27af396d2d5bf913"
 
 
@@ -66,6 +66,12 @@ def parse():
     p.add_argument("--tc-iterations", type=int, default=10)
     p.add_argument("--tc-steps", type=int, default=40)
     p.add_argument("--tc-precision", choices=["bf16x3", "fp64"], default="bf16x3")
+    p.add_argument("--jump", type=int, default=0, metavar="DCUT",
+                   help="energy and magnetisation jumps at --jump-tc from flows at T_c -/+ --jump-dt")
+    p.add_argument("--jump-tc", type=float, default=0.0)
+    p.add_argument("--jump-dt", type=str, default="0.004,0.008,0.012")
+    p.add_argument("--jump-steps", type=int, default=40)
+    p.add_argument("--jump-precision", choices=["bf16x3", "fp64"], default="bf16x3")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain device copy of 2 GiB (for scaling HBM byte counters)")
     return p.parse_args()
@@ -211,6 +217,31 @@ def tc_run(a):
         print(json.dumps(line), flush=True)
 
 
+def jump_run(a):
+    """Delta E and Delta m at T_c(Dcut) (Sec. 3): per temperature one flow at
+    h = 0 (energy) and two at h = 1e-9, 2e-9 (magnetisation, continued to
+    h -> 0); straight lines from both sides evaluated at T_c."""
+    from paper_1906_06060_amd import hotrg as H
+    from paper_1906_06060_amd import jump
+    prec = H.BF16X3 if a.jump_precision == "bf16x3" else H.FP64
+    dts = [float(v) for v in a.jump_dt.split(",")]
+    temps = sorted([a.jump_tc - d for d in dts] + [a.jump_tc + d for d in dts])
+    pts = []
+    t0 = time.perf_counter()
+    for T in temps:
+        t1 = time.perf_counter()
+        pts.append(jump.point(1.0 / T, a.jump, a.jump_steps, 1e-9, 2e-9, prec))
+        print(f"[jump] Dcut={a.jump} T={T:.6f} e={pts[-1]['e']:.9f} m={pts[-1]['m']:.9f} "
+              f"X={pts[-1]['X']:.4f} ({time.perf_counter() - t1:.1f} s)", file=sys.stderr, flush=True)
+    r = jump.jumps_from_points(pts, a.jump_tc)
+    print(json.dumps({"metric": "first-order jumps at T_c(Dcut)", "unit": "per site", "higher_is_better": None,
+                      "config": {"workload": f"4D Ising HOTRG with impurities, Dcut={a.jump}, {a.jump_steps} steps "
+                                             f"(lattice {2 ** (a.jump_steps // 4)}^4), {a.jump_precision}, "
+                                             f"h = 0 / 1e-9 / 2e-9", "T_c": a.jump_tc, "dT": dts},
+                      **r, "points": pts, "flows": 3 * len(temps),
+                      "total_s": round(time.perf_counter() - t0, 2)}), flush=True)
+
+
 def table_run(a):
     """Per Dcut and precision: one steady-state forward step with impurities
     (after the three ramp-up steps), and the reverse pass of a checkpointed
@@ -291,6 +322,9 @@ def main():
         return
     if a.tc:
         tc_run(a)
+        return
+    if a.jump:
+        jump_run(a)
         return
     from paper_1906_06060_amd import hotrg as H
     prec = H.BF16X3 if a.precision == "bf16x3" else H.FP64

@@ -321,3 +321,38 @@ def test_d2_x_bisection_brackets_onsager_beta_c():
     # the disordered side X below the threshold
     for b, x in r["points"]:
         assert (x > 1.5) == (b >= r["beta_hi"])
+
+
+# ---------------------------------------------------------------------------
+# Energy and magnetisation jumps (Sec. 3): the zero-field limit of m against
+# Onsager's spontaneous magnetisation, and the two-sided straight-line jumps
+# against the same lines drawn through Onsager's closed forms.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("beta,rel", [(0.5, 1e-4), (0.6, 1e-6)])
+def test_zero_field_magnetisation_equals_onsager(beta, rel):
+    from oracle import jump
+    m0, m1, m2 = jump.spontaneous_m(beta, 8, 2, 40)
+    assert m0 == pytest.approx(X.onsager_magnetization(beta), rel=rel)
+
+
+def test_zero_field_magnetisation_vanishes_when_disordered():
+    from oracle import jump
+    m0, m1, m2 = jump.spontaneous_m(0.40, 8, 2, 40)
+    assert m1 > 1e-10 and m2 == pytest.approx(2 * m1, rel=1e-6)
+    assert abs(m0) < 1e-3 * m1
+
+
+def test_d2_two_sided_lines_match_onsager_lines():
+    from oracle import jump
+    t_c = 2.0 / math.log(1.0 + math.sqrt(2.0))
+    temps = [1.8, 1.9, 2.6, 2.7]
+    r = jump.jumps(8, 2, t_c, temps, 40)
+
+    def at_tc(ts, ys):
+        a, b = np.polyfit(ts, ys, 1)
+        return a * t_c + b
+
+    e = [X.onsager_energy(1.0 / T) for T in temps]
+    m = [X.onsager_magnetization(1.0 / T) if T < t_c else 0.0 for T in temps]
+    assert r["delta_e"] == pytest.approx(at_tc(temps[2:], e[2:]) - at_tc(temps[:2], e[:2]), abs=5e-3)
+    assert r["delta_m"] == pytest.approx(at_tc(temps[:2], m[:2]) - at_tc(temps[2:], m[2:]), abs=1e-4)
