@@ -26,7 +26,7 @@ PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
 # HBM bytes per dispatch of the bf16x3 GEMM at this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # plain 2 GiB copy); valid only while the kernel source is the one profiled.
-GEMM_TRAFFIC_BYTES = 325945601482
+GEMM_TRAFFIC_BYTES = 332378747839
 GEMM_TRAFFIC_SRC_SHA = "27af396d2d5bf913"
 
 

@@ -63,7 +63,9 @@ typedef struct {
 /* Set up the one-site state of Eqs. (2.2) and (2.6) with bond dimension 2:
  *   W = [[sqrt cosh b, sqrt sinh b], [sqrt cosh b, -sqrt sinh b]] (W W^T = bond matrix, Eq. (2.1)),
  *   T^(0) = sum_s e^{b h s} prod_8 W[s, i],  S^(0) = same with an extra factor s,
- * normalised by c_0 = |T^(0)|_F.  beta >= 0 (ferromagnetic), h finite, dcut >= 1.
+ * normalised by c_0 = |T^(0)|_F.  beta >= 0 (ferromagnetic), h finite, 1 <= dcut <= 12
+ * (HOTRG_EINVAL otherwise): the environment matrices are at most dcut^2 x dcut^2, and the
+ * Gram, eigensolver and adjoint kernels use LDS tiles and buffers sized for 144 rows.
  * hotrg_init uses the defaults (FP64, impurities on, no checkpoints). */
 int hotrg_init(double beta, double h, int dcut, hotrg_ctx **out);
 int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotrg_ctx **out);

@@ -320,10 +320,11 @@ struct XP {
                max_out < out_avail && max_out < (1ull << 32);
     }
     // bf16 outputs go to the packed GEMM layout of a row-major operand with row length ld
-    void packed(uint64_t ld) {
+    void packed(uint64_t ld, uint32_t row0 = 0) {
         p.pack = 1;
         p.pld = make_fastdiv((uint32_t)ld);
         p.pkb = (uint32_t)(ld / PACK_K);
+        p.prow0 = row0;
     }
     const ExpandParams &done() {
         p.threads = (uint32_t)threads;
@@ -615,6 +616,9 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     const uint64_t ld = mixed ? (Ks + 63) / 64 * 64 : Ks;
     const uint64_t slice = M * ld;          // row-major operand slice of one tensor
     const uint64_t pslice = packed_rows(M) * ld;  // the same in the packed bf16 layout
+    // when every A tensor multiplies the same B, their rows form one packed
+    // block of nA * M rows (padded once, not per tensor) and one GEMM call
+    const bool stack = mixed && nB == 1 && nA > 1;
     double *Asl = nullptr, *Bsl = nullptr;
     uint16_t *Ah = nullptr, *Al = nullptr, *Bh = nullptr, *Bl = nullptr;
     if (mixed) {
@@ -707,7 +711,10 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.loops(kc, 1, ld, Dc, kc, 1);
                     x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
                     if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
-                    if (mixed) {
+                    if (mixed && stack) {  // rows t*M .. t*M + M - 1 of one packed block
+                        x.packed(ld, (uint32_t)(t * M));
+                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, Ah, Al, c->stream);
+                    } else if (mixed) {
                         x.packed(ld);
                         launch_iso_expand(x.done(), c->y2, Uc, nullptr, Ah + pslice * t, Al + pslice * t,
                                           c->stream);
@@ -774,7 +781,10 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                 hipEvent_t e0 = next_event(c), e1 = next_event(c);
                 if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
                 double *Cp = c->cbuf + (size_t)row0 * M * M;
-                if (mixed)
+                if (mixed && stack)
+                    launch_gemm_bf16x3(Ah, Al, Bh, Bl, Cp, (int)(M * rows), 1, (int)M, (int)ld, M,
+                                       first_slice ? 0 : 1, c->stream);
+                else if (mixed)
                     launch_gemm_bf16x3(Ah + pslice * row0, Al + pslice * row0, Bh + pslice * bidx, Bl + pslice * bidx,
                                        Cp, (int)M, rows, (int)M, (int)ld, M, first_slice ? 0 : 1, c->stream);
                 else

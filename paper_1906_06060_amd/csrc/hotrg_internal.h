@@ -88,6 +88,7 @@ struct ExpandParams {
     int pack;
     FastDiv pld;
     uint32_t pkb;
+    uint32_t prow0;  // packed layout: row of the operand block where this launch's row 0 goes
 };
 
 // Generic contraction of two strided views (reverse pass):

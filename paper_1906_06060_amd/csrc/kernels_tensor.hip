@@ -2,6 +2,7 @@
 // leg permutations, isometry (mode) products, norms, traces, Grams and the
 // squeezed environments.  All FP64; every reduction runs in a fixed order so
 // repeated runs are bitwise identical.
+#include <utility>
 #include "hotrg_internal.h"
 
 namespace hotrg {
@@ -187,8 +188,9 @@ void launch_mode_product_vec(const VecModeParams &p, const double *in, const dou
 // row-major operand offset -> packed GEMM layout (identity when not packed)
 __device__ __forceinline__ size_t split_offset(const ExpandParams &p, uint32_t o) {
     if (!p.pack) return o;
-    const uint32_t r = fast_div(o, p.pld);
-    const uint32_t k = o - r * p.pld.d;
+    const uint32_t q = fast_div(o, p.pld);
+    const uint32_t k = o - q * p.pld.d;
+    const uint32_t r = q + p.prow0;
     return ((size_t)(r / PACK_ROWS) * p.pkb + k / PACK_K) * (PACK_ROWS * PACK_K) + (r % PACK_ROWS) * PACK_K +
            k % PACK_K;
 }
@@ -487,9 +489,18 @@ void launch_iso_expand_pairs(const ExpandParams &p, bool run, const double *in, 
     else iso_expand_pairs_kernel<false, N><<<g, kThreads, lds, s>>>(p, in, U, hi, lo);
 }
 
-void launch_iso_expand(const ExpandParams &p, const double *in, const double *U, double *out, uint16_t *hi,
+void launch_iso_expand(const ExpandParams &pin, const double *in, const double *U, double *out, uint16_t *hi,
                        uint16_t *lo, hipStream_t s) {
-    if (p.threads == 0) return;
+    if (pin.threads == 0) return;
+    // The two output loops enter the product symmetrically; when the first
+    // one has unit output stride, exchange them so that the run kernels
+    // (unit stride on the second loop) apply.
+    ExpandParams p = pin;
+    if (p.o1 == 1 && p.o2 != 1 && p.L1 > 1 && p.nsum == p.L1) {
+        std::swap(p.L1, p.L2);
+        std::swap(p.u1, p.u2);
+        std::swap(p.o1, p.o2);
+    }
     if (hi && ((uintptr_t)hi & 3) == 0 && ((uintptr_t)lo & 3) == 0 && iso_pairs_ok(p, p.o2 == 1)) {
         const bool run = p.o2 == 1;
         switch (p.L2) {
