@@ -352,6 +352,7 @@ def main():
     elapsed = time.perf_counter() - t0
     ob = ctx.observables()
     st = ctx.gemm_stats()
+    ph = ctx.phase_stats()
     ctx.close()
 
     rows = (3 if imp else 1) * D ** 4
@@ -398,6 +399,14 @@ def main():
             "launches": st["launches"],
             "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 3),
         },
+    }
+    n_ph = max(ph["steps"], 1)
+    line["phases_ms_per_step"] = {
+        "isometries": round(ph["isometries_ms"] / n_ph, 2),
+        "contraction": round(ph["contraction_ms"] / n_ph, 2),
+        "of_which_gemm": round(ph["gemm_ms"] / n_ph, 2),
+        "operand_products": round((ph["contraction_ms"] - ph["gemm_ms"]) / n_ph, 2),
+        "normalise_permute": round(ph["normalise_ms"] / n_ph, 2),
     }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(D, a.cpu_rows)

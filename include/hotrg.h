@@ -144,9 +144,15 @@ int hotrg_step_with_isometries(hotrg_ctx *ctx, int axis, const double *const U[4
 int hotrg_get_isometry(hotrg_ctx *ctx, int q, double *out, size_t count, int *rows, int *cols);
 int hotrg_get_spectrum(hotrg_ctx *ctx, int q, int side, double *out, size_t count, int *len);
 
-/* Accumulated device time (ms, HIP events on the context stream) and launch
- * count of the contraction GEMM since the last reset, plus the algorithmic
- * flops those launches covered (2 M N K summed). kernel 0 = contraction GEMM. */
+/* Accumulated device time (ms, HIP events on the context stream) since the
+ * last reset.  kernel 0: the contraction GEMM launches (launches = their count,
+ * flops = 2 M N K summed).  kernel 1..3: the phases of hotrg_step, measured
+ * between events recorded at its start, after the isometries (environments,
+ * eigendecomposition, cut; Sec. 2), after the contraction (operand products
+ * and GEMMs) and after the normalisation and permutation: 1 = isometries,
+ * 2 = contraction (flops = the GEMM flops), 3 = normalisation; launches = steps
+ * counted.  Phase times include device idle time while the host decides the
+ * cut.  Querying a phase waits for the last step to finish. */
 int hotrg_kernel_stats(hotrg_ctx *ctx, int kernel, double *ms, long long *launches, double *flops);
 int hotrg_reset_stats(hotrg_ctx *ctx);
 

@@ -104,6 +104,12 @@ struct hotrg_ctx {
     long long gemm_launches = 0;
     double gemm_flops = 0;
     size_t device_bytes = 0;
+    // phase timing of hotrg_step: events at the start, after the isometries,
+    // after the contraction and after the normalisation (device timeline)
+    hipEvent_t ph[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ph_pending = false;
+    double phase_ms[3] = {0, 0, 0};
+    long long phase_steps = 0;
 
     // per-step checkpoints for the reverse pass (keep_checkpoints = 1)
     struct Checkpoint {
@@ -899,10 +905,28 @@ int save_checkpoint(hotrg_ctx *c, int axis, const int tv[3], const int k[3], boo
     return HOTRG_OK;
 }
 
+// Adds the phase intervals of the last completed step (waits for its end).
+int flush_phases(hotrg_ctx *c) {
+    if (!c->ph_pending) return HOTRG_OK;
+    c->ph_pending = false;
+    HIP_TRY(c, hipEventSynchronize(c->ph[3]));
+    for (int i = 0; i < 3; ++i) {
+        float ms = 0;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ph[i], c->ph[i + 1]));
+        c->phase_ms[i] += ms;
+    }
+    c->phase_steps++;
+    return HOTRG_OK;
+}
+
 int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost) {
     if (!c) return set_err(HOTRG_EINVAL, "null context");
     if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
     if (axis < 0 || axis > 3) return set_err(HOTRG_EINVAL, "axis must be 0..3");
+    TRY(flush_phases(c));
+    if (!c->ph[0])
+        for (auto &e : c->ph) HIP_TRY(c, hipEventCreate(&e));
+    HIP_TRY(c, hipEventRecord(c->ph[0], c->stream));
     int tv[3];
     transverse_of(axis, tv);
     uint64_t cst[8];
@@ -937,8 +961,12 @@ int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost
         TRY(isometries(c, c->state[0], lst, ldim, tv, axis, k));
     }
     if (c->cfg.keep_checkpoints) TRY(save_checkpoint(c, axis, tv, k, Uhost != nullptr));
+    HIP_TRY(c, hipEventRecord(c->ph[1], c->stream));
     TRY(contract(c, axis, tv, k));
+    HIP_TRY(c, hipEventRecord(c->ph[2], c->stream));
     TRY(finish_step(c, axis, tv, k));
+    HIP_TRY(c, hipEventRecord(c->ph[3], c->stream));
+    c->ph_pending = true;
     if (c->cfg.keep_checkpoints) {
         c->pending.c = c->last_cn;
         c->ckpts.push_back(c->pending);
@@ -1702,6 +1730,8 @@ void hotrg_free(hotrg_ctx *c) {
     for (auto &o : c->owned)
         if (o.p) (void)hipFree(o.p);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto e : c->ph)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -1777,15 +1807,25 @@ int hotrg_get_spectrum(hotrg_ctx *c, int q, int side, double *out, size_t count,
 }
 
 int hotrg_kernel_stats(hotrg_ctx *c, int kernel, double *ms, long long *launches, double *flops) {
-    if (!c || kernel != 0) return set_err(HOTRG_EINVAL, "bad argument");
-    if (ms) *ms = c->gemm_ms;
-    if (launches) *launches = c->gemm_launches;
-    if (flops) *flops = c->gemm_flops;
+    if (!c || kernel < 0 || kernel > 3) return set_err(HOTRG_EINVAL, "bad argument");
+    if (kernel == 0) {
+        if (ms) *ms = c->gemm_ms;
+        if (launches) *launches = c->gemm_launches;
+        if (flops) *flops = c->gemm_flops;
+        return HOTRG_OK;
+    }
+    TRY(flush_phases(c));
+    if (ms) *ms = c->phase_ms[kernel - 1];
+    if (launches) *launches = c->phase_steps;
+    if (flops) *flops = kernel == 2 ? c->gemm_flops : 0.0;
     return HOTRG_OK;
 }
 
 int hotrg_reset_stats(hotrg_ctx *c) {
     if (!c) return set_err(HOTRG_EINVAL, "null context");
+    TRY(flush_phases(c));
+    for (double &m : c->phase_ms) m = 0;
+    c->phase_steps = 0;
     c->gemm_ms = 0;
     c->gemm_launches = 0;
     c->gemm_flops = 0;

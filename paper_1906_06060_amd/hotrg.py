@@ -242,6 +242,19 @@ class Context:
         _check(_lib.hotrg_kernel_stats(self._h, 0, C.byref(ms), C.byref(ln), C.byref(fl)))
         return dict(ms=ms.value, launches=ln.value, flops=fl.value)
 
+    def phase_stats(self):
+        """Device ms per phase of hotrg_step since the last reset (kernels 1..3),
+        the GEMM ms (kernel 0) and the number of steps counted."""
+        out = {}
+        for kern, name in ((1, "isometries_ms"), (2, "contraction_ms"), (3, "normalise_ms"), (0, "gemm_ms")):
+            ms, fl = C.c_double(), C.c_double()
+            ln = C.c_longlong()
+            _check(_lib.hotrg_kernel_stats(self._h, kern, C.byref(ms), C.byref(ln), C.byref(fl)))
+            out[name] = ms.value
+            if kern == 1:
+                out["steps"] = ln.value
+        return out
+
     def reset_stats(self):
         _check(_lib.hotrg_reset_stats(self._h))
 
