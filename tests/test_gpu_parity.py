@@ -93,6 +93,46 @@ def test_contraction_full_tensor_fp64(H, dims, dcut, axis, ks, n0, budget):
         np.testing.assert_allclose(g, w, rtol=0, atol=1e-13 * max(np.abs(w).max(), 1e-300))
 
 
+@pytest.mark.parametrize("dims,dcut,axis,ks", CASES)
+@pytest.mark.parametrize("n0", [0, 3])
+def test_contraction_full_tensor_bf16x3(H, dims, dcut, axis, ks, n0):
+    # every entry of T', S_m', S_e' on ragged shapes: odd bond dims (the paired
+    # operand writes fall back), stacked A rows at offsets that are not
+    # multiples of 256 (e.g. 250 rows per tensor), K padded to 64
+    T = synth.z2_tensor(dims, seed=111)
+    Sm = synth.z2_tensor(dims, seed=112, odd=True)
+    Se = synth.z2_tensor(dims, seed=113)
+    tv = [q for q in range(4) if q != axis]
+    Us = {}
+    for j, q in enumerate(tv):
+        n = dims[q] ** 2
+        k = min(dcut, n) if ks is None else ks[j]
+        Us[q] = synth.isometry(n, k, seed=210 + q)
+    with H.Context(0.2, 0.0, dcut, precision=H.BF16X3, mixed_from_step=1) as ctx:
+        ctx.set_state(T, Sm, Se, n=n0, lnz_acc=0.0)
+        ctx.step_with_isometries(axis, Us)
+        cn = ctx.observables()["last_cn"]
+        got = [ctx.tensor(w) for w in range(3)]
+    rshape = tuple(Us[q].shape[1] for q in tv) + (dims[axis],)
+    idx_all = [tuple(int(v) for v in np.unravel_index(f, rshape)) for f in range(int(np.prod(rshape)))]
+    pairs = [(T, T), (Sm, T), (Se, Se if n0 == 0 else T)]
+    worst = 0.0
+    for (T1, T2), G in zip(pairs, got):
+        ent, rn, cnorm = OS.step_entries_with_norms(T1, T2, Us, axis, idx_all, idx_all)
+        for i, r in enumerate(idx_all):
+            for j, cc in enumerate(idx_all):
+                idx = [0] * 8
+                for q_i, q in enumerate(tv):
+                    idx[2 * q], idx[2 * q + 1] = r[q_i], cc[q_i]
+                idx[2 * axis], idx[2 * axis + 1] = r[-1], cc[-1]
+                scale = rn[i] * cnorm[j]
+                if scale > 0:
+                    worst = max(worst, abs(G[tuple(idx)] * cn - ent[i, j]) / scale)
+                else:
+                    assert G[tuple(idx)] == 0.0
+    assert worst <= 6e-5, worst
+
+
 def _sampled_parity(H, D, axis, precision, impurities, nrows, bound, seed=7, slice_budget=0):
     dims = (D, D, D, D)
     T = synth.z2_tensor(dims, seed=seed)
