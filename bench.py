@@ -398,6 +398,9 @@ def main():
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "launches": st["launches"],
             "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 3),
+            "launch": ("one GEMM call per K slice: a main dispatch over whole rounds of tiles, a tail dispatch "
+                       "running the last partial round as k-halves, and gemm_tail_fixup_kernel"
+                       if prec == H.BF16X3 else "one gemm_f64_kernel dispatch per K slice"),
         },
     }
     n_ph = max(ph["steps"], 1)

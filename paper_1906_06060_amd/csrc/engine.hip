@@ -87,6 +87,7 @@ struct hotrg_ctx {
     double *obs = nullptr;                        // 3 + 144
     DevBuf f64_slices;                            // FP64 operand slices
     DevBuf x3_slices;                             // bf16 hi/lo operand slices
+    DevBuf gemm_tail;                             // second k-halves of the GEMM's last round of tiles
     std::vector<DevBuf> owned;
 
     // host-side record of the last step
@@ -627,8 +628,11 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     const bool stack = mixed && nB == 1 && nA > 1;
     double *Asl = nullptr, *Bsl = nullptr;
     uint16_t *Ah = nullptr, *Al = nullptr, *Bh = nullptr, *Bl = nullptr;
+    double *tail = nullptr;
     if (mixed) {
         TRY(ensure(c, c->x3_slices, sizeof(uint16_t) * 2 * pslice * (nA + nB)));
+        TRY(ensure(c, c->gemm_tail, sizeof(double) * GEMM_TAIL_MAX_TILES * 256 * 256));
+        tail = (double *)c->gemm_tail.p;
         Ah = (uint16_t *)c->x3_slices.p;
         Al = Ah + pslice * nA;
         Bh = Al + pslice * nA;
@@ -789,10 +793,10 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                 double *Cp = c->cbuf + (size_t)row0 * M * M;
                 if (mixed && stack)
                     launch_gemm_bf16x3(Ah, Al, Bh, Bl, Cp, (int)(M * rows), 1, (int)M, (int)ld, M,
-                                       first_slice ? 0 : 1, c->stream);
+                                       first_slice ? 0 : 1, c->stream, tail);
                 else if (mixed)
                     launch_gemm_bf16x3(Ah + pslice * row0, Al + pslice * row0, Bh + pslice * bidx, Bl + pslice * bidx,
-                                       Cp, (int)M, rows, (int)M, (int)ld, M, first_slice ? 0 : 1, c->stream);
+                                       Cp, (int)M, rows, (int)M, (int)ld, M, first_slice ? 0 : 1, c->stream, tail);
                 else
                     launch_gemm_f64(Asl + slice * row0, Bsl + slice * bidx, Cp, (int)(M * rows), (int)M, (int)Ks, Ks,
                                     Ks, M, first_slice ? 0 : 1, c->stream);
@@ -1084,9 +1088,12 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
     const uint64_t pC = packed_rows(M) * ldM, pK = packed_rows(Ks) * ldM;
     uint16_t *Ch = nullptr, *Cl = nullptr, *CTh = nullptr, *CTl = nullptr;
     uint16_t *ATh = nullptr, *ATl = nullptr, *BTh = nullptr, *BTl = nullptr;
+    double *tail = nullptr;
     if (mixed) {
         if (M * ldM >= (1ull << 32) || Ks * ldM >= (1ull << 31))
             return set_err(HOTRG_ENOMEM, "reverse pass: packed operand exceeds 2^31 elements");
+        TRY(ensure(c, c->gemm_tail, sizeof(double) * GEMM_TAIL_MAX_TILES * 256 * 256));
+        tail = (double *)c->gemm_tail.p;
         uint16_t *x3;
         TRY(bw_buf(c, BW_X3, 4 * pC + 4 * pK, &x3));
         Ch = x3;
@@ -1259,8 +1266,8 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
             }
             // ---- A_bar = C_bar B, B_bar = C_bar^T A (FP64, or bf16x3 in mixed precision)
             if (mixed) {
-                launch_gemm_bf16x3(Ch, Cl, BTh, BTl, Abar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream);
-                launch_gemm_bf16x3(CTh, CTl, ATh, ATl, Bbar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream);
+                launch_gemm_bf16x3(Ch, Cl, BTh, BTl, Abar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream, tail);
+                launch_gemm_bf16x3(CTh, CTl, ATh, ATl, Bbar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream, tail);
             } else {
                 launch_gemm_f64(Cbar, BT, Abar, (int)M, (int)Ks, (int)M, M, M, Ks, 0, c->stream);
                 launch_gemm_f64(CbarT, AT, Bbar, (int)M, (int)Ks, (int)M, M, M, Ks, 0, c->stream);

@@ -26,12 +26,15 @@ namespace hotrg {
 typedef float flt16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// blockIdx.x -> (tile row, tile col): round-robin XCD dispatch undone, then
-// groups of `G` tile rows walked column by column.
-__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn) {
-    const int nb = tiles_m * tiles_n;
+// Round-robin XCD dispatch undone: consecutive units run on one XCD.
+__device__ __forceinline__ int unit_of(int bid, int nb) {
     const int full = nb - nb % 8;
-    int t = bid < full ? (bid % 8) * (full / 8) + bid / 8 : bid;
+    return bid < full ? (bid % 8) * (full / 8) + bid / 8 : bid;
+}
+
+// Tile index t -> (tile row, tile col): groups of `G` tile rows walked column
+// by column.
+__device__ __forceinline__ void tile_rc(int t, int tiles_m, int tiles_n, int &tm, int &tn) {
     const int G = 8;
     const int per_group = G * tiles_n;
     const int group = t / per_group;
@@ -40,6 +43,11 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &
     const int r = t % per_group;
     tm = first + r % gsize;
     tn = r / gsize;
+}
+
+// blockIdx.x -> (tile row, tile col) for a launch covering every tile.
+__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn) {
+    tile_rc(unit_of(bid, tiles_m * tiles_n), tiles_m, tiles_n, tm, tn);
 }
 
 // ------------------------------------------------------------------ FP64 ---
@@ -148,20 +156,34 @@ static_assert(KC % BK == 0, "a chunk is whole stages");
 //
 // A holds `ntA` tensors of M rows, each padded to Mp = roundup(M, 256); a row
 // tile never straddles two tensors and its rows map to C rows t M + r (r < M).
+//
+// One launch covers the tiles t0 .. t0 + units - 1 of the tile order.  With
+// halves = 2 every tile is two units: k in [0, kmid) added into C as usual,
+// and k in [kmid, K) written to the 256 x 256 block `part` + (unit / 2) 2^16,
+// which gemm_tail_fixup_kernel adds into C afterwards (used for the last,
+// partly filled round of tiles, so that it takes half as long).
 __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restrict__ Ah,
                                                          const uint16_t *__restrict__ Al,
                                                          const uint16_t *__restrict__ Bh,
                                                          const uint16_t *__restrict__ Bl, double *__restrict__ C,
                                                          int M, int Mp, int N, int K, size_t ldc, int accumulate,
-                                                         int tiles_m, int tiles_n) {
+                                                         int tiles_m, int tiles_n, int t0, int halves, int kmid,
+                                                         double *__restrict__ part) {
     extern __shared__ __align__(16) uint16_t smem[];
     char *lds = (char *)smem;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 2, wc = wave & 3;  // wave tile: rows wr*128.., cols wc*64..
+    const int u = unit_of(blockIdx.x, gridDim.x);
+    const int hf = halves == 2 ? (u & 1) : 0;
     int tm, tn;
-    tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    tile_rc(t0 + (halves == 2 ? (u >> 1) : u), tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     const int tens = m0 / Mp, lrow0 = m0 - tens * Mp;  // tensor of this row tile, its first local row
+    const int kbeg = hf ? kmid : 0, kend = (halves == 2 && !hf) ? kmid : K;
+    // destination of this unit: its C tile (clipped to M x N) or its partial block
+    double *const Cd = hf ? part + (size_t)(u >> 1) * (BM * BN) : C + (size_t)(tens * M + lrow0) * ldc + n0;
+    const size_t ldd = hf ? (size_t)BN : ldc;
+    const int rlim = hf ? BM : M - lrow0, clim = hf ? BN : N - n0;
 
     // loads: wave w brings half w % 2 (128 rows, 8 KB) of operand w / 2
     const size_t kb = (size_t)K / BK;  // packed k blocks per row tile
@@ -227,7 +249,7 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     // Add the FP32 partial tile into the FP64 output: in four passes (one per
     // 32-row block of every wave) the accumulators go through LDS and all
     // threads then update C with coalesced row segments.
-    bool first = !accumulate;
+    bool first = hf ? true : !accumulate;
     float *sC = (float *)smem;
     constexpr int SROW = 65;
     auto flush = [&]() {
@@ -247,10 +269,10 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
                 const int idx = tid + NT * q;
                 const int w = idx >> 11, rem = idx & 2047;
                 const int rl = rem >> 6, cl = rem & 63;
-                const int lrow = lrow0 + (w >> 2) * 128 + i * 32 + rl;
-                const int col = n0 + (w & 3) * 64 + cl;
-                if (lrow < M && col < N) {
-                    double *c = C + (size_t)(tens * M + lrow) * ldc + col;
+                const int lr = (w >> 2) * 128 + i * 32 + rl;
+                const int lc = (w & 3) * 64 + cl;
+                if (lr < rlim && lc < clim) {
+                    double *c = Cd + (size_t)lr * ldd + lc;
                     double v = (double)sC[w * 32 * SROW + rl * SROW + cl];
                     *c = first ? v : *c + v;
                 }
@@ -268,8 +290,8 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     // chunk the refill reloads a valid block and the fragments read are not
     // used), so the scheduling groups below can place one LDS read (and, in
     // the second substep, one global load) between every two MFMAs.
-    for (int kc0 = 0; kc0 < K; kc0 += KC) {
-        const int nst = (min(K, kc0 + KC) - kc0) / BK;
+    for (int kc0 = kbeg; kc0 < kend; kc0 += KC) {
+        const int nst = (min(kend, kc0 + KC) - kc0) / BK;
         const size_t b0 = (size_t)kc0 / BK, blast = kb - 1;
         issue(b0, 0);
         __syncthreads();  // (waits for this wave's loads) stage 0 landed everywhere
@@ -308,21 +330,57 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     }
     if (first) flush();
 }
+
+// C tile of split tile s (tile t0 + s) += its second-half partial block.
+__global__ void __launch_bounds__(256) gemm_tail_fixup_kernel(const double *__restrict__ part, double *__restrict__ C,
+                                                              int M, int Mp, int N, size_t ldc, int tiles_m,
+                                                              int tiles_n, int t0) {
+    const int s = blockIdx.x;
+    int tm, tn;
+    tile_rc(t0 + s, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tens = m0 / Mp, lrow0 = m0 - tens * Mp;
+    const double *p = part + (size_t)s * (BM * BN);
+    for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
+        const int lr = e / BN, lc = e % BN;
+        if (lrow0 + lr < M && n0 + lc < N) C[(size_t)(tens * M + lrow0 + lr) * ldc + n0 + lc] += p[e];
+    }
+}
 }  // namespace x3
 
 void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl, double *C,
-                        int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s) {
+                        int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s, double *part) {
     if (M <= 0 || N <= 0 || ntA <= 0) return;
     static bool attr_set = false;
+    static int ncu = 0;
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)x3::gemm_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)x3::LDS_BYTES);
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 0;
         attr_set = true;
     }
     const int Mp = (M + x3::BM - 1) / x3::BM * x3::BM;
     const int tm = ntA * (Mp / x3::BM), tn = (N + x3::BN - 1) / x3::BN;
-    x3::gemm_bf16x3_kernel<<<tm * tn, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, Mp, N, K, ldc, accumulate,
-                                                                  tm, tn);
+    const int tiles = tm * tn;
+    // One workgroup per CU at a time: the last round of tiles is partly
+    // filled.  When it holds at most half the CUs (and there is a full round
+    // before it), its tiles run as two k-halves each, after the full rounds.
+    const int rem = ncu > 0 ? tiles % ncu : 0;
+    const int kmid = K / 2 / x3::BK * x3::BK;
+    if (part && rem > 0 && rem <= ncu / 2 && rem <= GEMM_TAIL_MAX_TILES && tiles > ncu && kmid > 0) {
+        const int main = tiles - rem;
+        x3::gemm_bf16x3_kernel<<<main, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, Mp, N, K, ldc, accumulate,
+                                                                   tm, tn, 0, 1, K, nullptr);
+        x3::gemm_bf16x3_kernel<<<2 * rem, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, Mp, N, K, ldc,
+                                                                      accumulate, tm, tn, main, 2, kmid, part);
+        x3::gemm_tail_fixup_kernel<<<rem, 256, 0, s>>>(part, C, M, Mp, N, ldc, tm, tn, main);
+        return;
+    }
+    x3::gemm_bf16x3_kernel<<<tiles, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, Mp, N, K, ldc, accumulate, tm,
+                                                                tn, 0, 1, K, nullptr);
 }
 
 }  // namespace hotrg

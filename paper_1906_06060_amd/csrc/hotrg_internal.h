@@ -205,7 +205,11 @@ __host__ __device__ inline size_t packed_offset(size_t r, size_t k, size_t K) {
            k % PACK_K;
 }
 inline size_t packed_rows(size_t R) { return (R + PACK_ROWS - 1) / PACK_ROWS * PACK_ROWS; }
+// `part` (may be null): scratch for the second k-halves of the last, partly
+// filled round of tiles, GEMM_TAIL_MAX_TILES blocks of 256 x 256 doubles.
+constexpr int GEMM_TAIL_MAX_TILES = 128;
 void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl,
-                        double *C, int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s);
+                        double *C, int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s,
+                        double *part);
 
 }  // namespace hotrg

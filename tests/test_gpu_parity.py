@@ -187,6 +187,13 @@ def test_contraction_sampled_d8_bf16x3_b1_slices(H):
     _sampled_parity(H, 8, 2, H.BF16X3, True, 16, 6e-5, seed=11, slice_budget=1)
 
 
+def test_contraction_sampled_d7_bf16x3_split_last_round(H):
+    # 3 x 7^4 stacked rows, 7^4 columns: 29 x 10 = 290 tiles of 256 x 256, so
+    # the last 34 run as two k-halves each (added through the partial buffer);
+    # half of the sampled S_e rows and most columns fall in those tiles
+    _sampled_parity(H, 7, 3, H.BF16X3, True, 24, 6e-5, seed=41)
+
+
 def test_contraction_sampled_d10_bf16x3_bench_configuration(H):
     w = _sampled_parity(H, 10, 3, H.BF16X3, True, 10, 6e-5, seed=31)
     print(f"bf16x3 D=10 worst scaled error {w:.3e}")
