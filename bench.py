@@ -23,11 +23,11 @@ sys.path.insert(0, ROOT)
 PEAK_BF16 = 2.5e15     # MI355X dense bf16 MFMA, flop/s
 PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
 
-# HBM bytes per dispatch of the bf16x3 GEMM at this workload, from two
+# HBM bytes per GEMM call (main + tail dispatch + fix-up) of the bf16x3 GEMM at this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # plain 2 GiB copy); valid only while the kernel source is the one profiled.
-GEMM_TRAFFIC_BYTES = 332378747839
-GEMM_TRAFFIC_SRC_SHA = "27af396d2d5bf913"
+GEMM_TRAFFIC_BYTES = 311375665375
+GEMM_TRAFFIC_SRC_SHA = "e87925238471c184"
 
 
 def gemm_source_sha():
@@ -395,7 +395,7 @@ def main():
             "issued_frac": round(issue * achieved / peak, 4),
             "traffic": (GEMM_TRAFFIC_BYTES if (gemm_source_sha() == GEMM_TRAFFIC_SRC_SHA and D == 10 and imp
                                                 and prec == H.BF16X3) else None),
-            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+            "traffic_unit": "bytes per GEMM call (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "launches": st["launches"],
             "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 3),
             "launch": ("one GEMM call per K slice: a main dispatch over whole rounds of tiles, a tail dispatch "
