@@ -145,8 +145,10 @@ int hotrg_get_isometry(hotrg_ctx *ctx, int q, double *out, size_t count, int *ro
 int hotrg_get_spectrum(hotrg_ctx *ctx, int q, int side, double *out, size_t count, int *len);
 
 /* Accumulated device time (ms, HIP events on the context stream) since the
- * last reset.  kernel 0: the contraction GEMM launches (launches = their count,
- * flops = 2 M N K summed).  kernel 1..3: the phases of hotrg_step, measured
+ * last reset.  kernel 0: the contraction GEMM calls, one per K slice and
+ * operand pairing (launches = their count, flops = 2 M N K summed); a bf16x3
+ * call whose last round of output tiles is partly filled runs as a main
+ * dispatch, a tail dispatch over that round split in k, and a small add.  kernel 1..3: the phases of hotrg_step, measured
  * between events recorded at its start, after the isometries (environments,
  * eigendecomposition, cut; Sec. 2), after the contraction (operand products
  * and GEMMs) and after the normalisation and permutation: 1 = isometries,
