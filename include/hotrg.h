@@ -148,8 +148,9 @@ int hotrg_get_spectrum(hotrg_ctx *ctx, int q, int side, double *out, size_t coun
  * last reset.  kernel 0: the contraction GEMM calls, one per K slice and
  * operand pairing (launches = their count, flops = 2 M N K summed); a bf16x3
  * call whose last round of output tiles is partly filled runs as a main
- * dispatch, a tail dispatch over that round split in k, and a small add.  kernel 1..3: the phases of hotrg_step, measured
- * between events recorded at its start, after the isometries (environments,
+ * dispatch, a tail dispatch over that round split in k, and a small add.
+ * kernel 1..3: the phases of hotrg_step, measured between events recorded at
+ * its start, after the isometries (environments,
  * eigendecomposition, cut; Sec. 2), after the contraction (operand products
  * and GEMMs) and after the normalisation and permutation: 1 = isometries,
  * 2 = contraction (flops = the GEMM flops), 3 = normalisation; launches = steps
