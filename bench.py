@@ -27,13 +27,19 @@ PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # plain 2 GiB copy); valid only while the kernel source is the one profiled.
 GEMM_TRAFFIC_BYTES = 311375665375
-GEMM_TRAFFIC_SRC_SHA = "e87925238471c184"
+GEMM_TRAFFIC_SRC_SHA = "bd6bbd792c297d0c"
+
+
+BF16X3_SECTION = "// ---------------------------------------------------------------- bf16x3 ---"
 
 
 def gemm_source_sha():
+    """sha256 prefix of the bf16x3 part of gemm.hip (from its section marker to
+    the end of the file), the source the stored traffic counters belong to."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1906_06060_amd", "csrc", "gemm.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(os.path.join(ROOT, "paper_1906_06060_amd", "csrc", "gemm.hip")) as f:
+        text = f.read()
+    return hashlib.sha256(text[text.index(BF16X3_SECTION):].encode()).hexdigest()[:16]
 
 
 def parse():

@@ -54,15 +54,17 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &
 namespace f64 {
 constexpr int BM = 128, BN = 128, BK = 16, PAD = 4, NT = 256;
 
-// Register-blocked DGEMM: a 16 x 16 thread grid, each thread owns rows
-// ty + 16 i and columns tx + 16 j (i, j < 8); operands staged k-major in LDS
-// so that a wave reads 4 broadcast A values and 16 consecutive B values per k.
+// Register-blocked DGEMM: a 16 x 16 thread grid, each thread owns the row
+// pairs 2 ty + 32 i + {0, 1} and the column pairs 2 tx + 32 j + {0, 1}
+// (i, j < 4); operands staged k-major in LDS, so every operand pair is one
+// 16-byte LDS read (a wave reads 4 broadcast A pairs and 16 consecutive B
+// pairs per k) and C is written in 16-byte pairs.
 __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__ A, const double *__restrict__ B,
                                                        double *__restrict__ C, int M, int N, int K, size_t lda,
                                                        size_t ldb, size_t ldc, int accumulate, int tiles_m,
                                                        int tiles_n) {
-    __shared__ double As[BK][BM + PAD];
-    __shared__ double Bs[BK][BN + PAD];
+    __shared__ __align__(16) double As[BK][BM + PAD];
+    __shared__ __align__(16) double Bs[BK][BN + PAD];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
@@ -98,9 +100,14 @@ __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__
         for (int kk = 0; kk < BK; ++kk) {
             double a[8], b[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) b[j] = Bs[kk][tx + 16 * j];
+            for (int i = 0; i < 4; ++i) {
+                const double2 va = *(const double2 *)&As[kk][2 * ty + 32 * i];
+                const double2 vb = *(const double2 *)&Bs[kk][2 * tx + 32 * i];
+                a[2 * i] = va.x;
+                a[2 * i + 1] = va.y;
+                b[2 * i] = vb.x;
+                b[2 * i + 1] = vb.y;
+            }
 #pragma unroll
             for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -110,11 +117,11 @@ __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int row = m0 + ty + 16 * i;
+        const int row = m0 + 2 * ty + 32 * (i >> 1) + (i & 1);
         if (row >= M) continue;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int col = n0 + tx + 16 * j;
+            const int col = n0 + 2 * tx + 32 * (j >> 1) + (j & 1);
             if (col < N) {
                 double *c = C + (size_t)row * ldc + col;
                 *c = accumulate ? *c + acc[i][j] : acc[i][j];
