@@ -120,6 +120,7 @@ namespace {
 constexpr int LP_JT = 32;
 constexpr int LP_MAXL = 16;
 constexpr int LP_UPT = 9;  // isometry-adjoint entries per thread: L N N <= 16 * 12 * 12 = 2304 = 256 * 9
+constexpr int LP_PB = 3;   // 2 x 2 entry blocks per thread with N even: 2304 / 4 = 576 <= 256 * 3
 }  // namespace
 
 template <int N>
@@ -128,22 +129,34 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
                                                               const double *__restrict__ U,
                                                               double *__restrict__ out,
                                                               double *__restrict__ partial) {
-    extern __shared__ double lp_sm[];
+    // With N even every operand pair below is one aligned 16-byte LDS read:
+    // the outputs take (j, l pair) per thread with U staged [l][c][s], the
+    // isometry adjoint takes 2 l x 2 (c, s) entries per thread.  Every sum
+    // keeps the order of the one-entry-per-thread form (odd N).
+    constexpr bool PAIRS = N % 2 == 0;
+    extern __shared__ __align__(16) double lp_sm[];
     const int L = p.L;
-    double *sU = lp_sm;                       // [l][s][c]  N * N * L
+    double *sU = lp_sm;                       // PAIRS: [l][c][s], else [l][s][c]   N * N * L
     double *sX = sU + N * N * L;              // [jj][c][s] JT * L * N
     double *sY = sX + LP_JT * L * N;          // [jj][l]    JT * N
     const int tid = threadIdx.x;
     const int nU = N * N * L;
     for (int u = tid; u < nU; u += blockDim.x) {
-        const int c = u % L, s = (u / L) % N, l = u / (L * N);
-        sU[u] = U[l * p.ul + s * p.us + c * p.uc];
+        if (PAIRS) {
+            const int s = u % N, c = (u / N) % L, l = u / (L * N);
+            sU[u] = U[l * p.ul + s * p.us + c * p.uc];
+        } else {
+            const int c = u % L, s = (u / L) % N, l = u / (L * N);
+            sU[u] = U[l * p.ul + s * p.us + c * p.uc];
+        }
     }
     const uint32_t o1 = blockIdx.x / p.n_o2, o2 = blockIdx.x % p.n_o2;
     const uint32_t xo = o1 * p.x_o1 + o2 * p.x_o2, oo = o1 * p.out_o1 + o2 * p.out_o2;
-    double pacc[LP_UPT];
+    double pacc[4 * LP_PB];  // >= LP_UPT
 #pragma unroll
-    for (int q = 0; q < LP_UPT; ++q) pacc[q] = 0.0;
+    for (int q = 0; q < 4 * LP_PB; ++q) pacc[q] = 0.0;
+    constexpr int NH = PAIRS ? N / 2 : 1;
+    const int nblk = PAIRS ? NH * (L * N / 2) : 0;  // 2 x 2 blocks of the isometry adjoint
     for (uint32_t j0 = 0; j0 < p.NJ; j0 += LP_JT) {
         __syncthreads();  // previous tile consumed (and sU staged on the first pass)
         for (int idx = tid; idx < LP_JT * L * N; idx += blockDim.x) {
@@ -157,35 +170,96 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
             sY[idx] = j < p.NJ ? Y[oo + j * p.oj + l * p.ol] : 0.0;
         }
         __syncthreads();
-        // outputs of the tile
-        for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
-            const int l = idx % N, jj = idx / N;
-            const uint32_t j = j0 + jj;
-            if (j >= p.NJ) continue;
-            const double *xr = sX + jj * L * N;
-            const double *ur = sU + l * N * L;
-            double acc = 0.0;
-            for (int c = 0; c < L; ++c)
+        if (PAIRS) {
+            // outputs (j, l) and (j, l + 1): sum over c, then s
+            for (int idx = tid; idx < LP_JT * NH; idx += blockDim.x) {
+                const int l = 2 * (idx % NH), jj = idx / NH;
+                const uint32_t j = j0 + jj;
+                if (j >= p.NJ) continue;
+                const double *xr = sX + jj * L * N;
+                const double *u0 = sU + l * L * N, *u1 = u0 + L * N;
+                double a0 = 0.0, a1 = 0.0;
+                for (int c = 0; c < L; ++c)
 #pragma unroll
-                for (int s = 0; s < N; ++s) acc = fma(ur[s * L + c], xr[c * N + s], acc);
-            out[oo + j * p.oj + l * p.ol] = acc;
+                    for (int s = 0; s < N; s += 2) {
+                        const double2 x2 = *(const double2 *)(xr + c * N + s);
+                        const double2 v0 = *(const double2 *)(u0 + c * N + s);
+                        const double2 v1 = *(const double2 *)(u1 + c * N + s);
+                        a0 = fma(v0.x, x2.x, a0);
+                        a0 = fma(v0.y, x2.y, a0);
+                        a1 = fma(v1.x, x2.x, a1);
+                        a1 = fma(v1.y, x2.y, a1);
+                    }
+                out[oo + j * p.oj + l * p.ol] = a0;
+                out[oo + j * p.oj + (l + 1) * p.ol] = a1;
+            }
+            // isometry adjoint: block b = (l pair, (c, s) pair), running sums over jj
+#pragma unroll
+            for (int q = 0; q < LP_PB; ++q) {
+                const int b = tid + q * (int)blockDim.x;
+                if (b >= nblk) break;
+                const int l = 2 * (b % NH), cs = 2 * (b / NH);
+                double a00 = pacc[4 * q], a01 = pacc[4 * q + 1], a10 = pacc[4 * q + 2], a11 = pacc[4 * q + 3];
+#pragma unroll 4
+                for (int jj = 0; jj < LP_JT; ++jj) {
+                    const double2 y = *(const double2 *)(sY + jj * N + l);
+                    const double2 x = *(const double2 *)(sX + jj * L * N + cs);
+                    a00 = fma(y.x, x.x, a00);
+                    a01 = fma(y.x, x.y, a01);
+                    a10 = fma(y.y, x.x, a10);
+                    a11 = fma(y.y, x.y, a11);
+                }
+                pacc[4 * q] = a00;
+                pacc[4 * q + 1] = a01;
+                pacc[4 * q + 2] = a10;
+                pacc[4 * q + 3] = a11;
+            }
+        } else {
+            // outputs of the tile
+            for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
+                const int l = idx % N, jj = idx / N;
+                const uint32_t j = j0 + jj;
+                if (j >= p.NJ) continue;
+                const double *xr = sX + jj * L * N;
+                const double *ur = sU + l * N * L;
+                double acc = 0.0;
+                for (int c = 0; c < L; ++c)
+#pragma unroll
+                    for (int s = 0; s < N; ++s) acc = fma(ur[s * L + c], xr[c * N + s], acc);
+                out[oo + j * p.oj + l * p.ol] = acc;
+            }
+            // isometry-adjoint running sums (padding rows of the tile are zero)
+#pragma unroll
+            for (int q = 0; q < LP_UPT; ++q) {
+                const int u = tid + q * (int)blockDim.x;
+                if (u >= nU) break;
+                const int c = u % L, s = (u / L) % N, l = u / (L * N);
+                double a = pacc[q];
+#pragma unroll 4
+                for (int jj = 0; jj < LP_JT; ++jj) a = fma(sY[jj * N + l], sX[(jj * L + c) * N + s], a);
+                pacc[q] = a;
+            }
         }
-        // isometry-adjoint running sums (padding rows of the tile are zero)
+    }
+    if (PAIRS) {
+#pragma unroll
+        for (int q = 0; q < LP_PB; ++q) {
+            const int b = tid + q * (int)blockDim.x;
+            if (b >= nblk) break;
+            const int l = 2 * (b % NH), cs = 2 * (b / NH);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int le = l + (e >> 1), cse = cs + (e & 1);
+                const int c = cse / N, s = cse % N;
+                partial[(size_t)blockIdx.x * nU + (le * N + s) * L + c] = pacc[4 * q + e];
+            }
+        }
+    } else {
 #pragma unroll
         for (int q = 0; q < LP_UPT; ++q) {
             const int u = tid + q * (int)blockDim.x;
-            if (u >= nU) break;
-            const int c = u % L, s = (u / L) % N, l = u / (L * N);
-            double a = pacc[q];
-#pragma unroll 4
-            for (int jj = 0; jj < LP_JT; ++jj) a = fma(sY[jj * N + l], sX[(jj * L + c) * N + s], a);
-            pacc[q] = a;
+            if (u < nU) partial[(size_t)blockIdx.x * nU + u] = pacc[q];
         }
-    }
-#pragma unroll
-    for (int q = 0; q < LP_UPT; ++q) {
-        const int u = tid + q * (int)blockDim.x;
-        if (u < nU) partial[(size_t)blockIdx.x * nU + u] = pacc[q];
     }
 }
 
