@@ -208,83 +208,6 @@ PermParams perm_params(int nd, const int *ext, const uint32_t *in_st, uint64_t *
     return p;
 }
 
-// Mode product description helper: output extents with (in stride, U stride)
-// per output dim, one contracted index.
-struct MP {
-    ModeParams p{};
-    uint64_t total = 1;
-    uint64_t max_in = 0, max_u = 0;  // largest element offsets the launch can touch
-    void dim(int ext, uint64_t ist, uint64_t ust) {
-        int k = p.nd++;
-        p.ext[k] = make_fastdiv((uint32_t)ext);
-        p.in_st[k] = (uint32_t)ist;
-        p.u_st[k] = (uint32_t)ust;
-        total *= (uint64_t)ext;
-        max_in += (uint64_t)(ext - 1) * ist;
-        max_u += (uint64_t)(ext - 1) * ust;
-    }
-    void sum(int n, uint64_t ist, uint64_t ust) {
-        p.nsum = n;
-        p.in_sum_st = (uint32_t)ist;
-        p.u_sum_st = (uint32_t)ust;
-        max_in += (uint64_t)(n - 1) * ist;
-        max_u += (uint64_t)(n - 1) * ust;
-    }
-    // host-side bounds check of a launch: input, isometry and output extents
-    // (elements available from each base pointer)
-    bool fits(uint64_t in_avail, uint64_t u_avail, uint64_t out_avail) const {
-        return p.nd <= MP_MAXD && total < (1ull << 31) && max_in < in_avail && max_u < u_avail &&
-               total <= out_avail && max_in < (1ull << 32);
-    }
-    const ModeParams &done() {
-        p.total = (uint32_t)total;
-        return p;
-    }
-};
-
-// Vectorised mode product description (see VecModeParams).
-struct VM {
-    VecModeParams p{};
-    uint64_t outer = 1, max_in = 0, max_u = 0;
-    bool both_j = false;
-    void dim(int ext, uint64_t ist, uint64_t ust) {
-        int k = p.nd++;
-        if (k >= MP_MAXD) return;
-        p.ext[k] = make_fastdiv((uint32_t)ext);
-        p.in_st[k] = (uint32_t)ist;
-        p.u_st[k] = (uint32_t)ust;
-        outer *= (uint64_t)ext;
-        max_in += (uint64_t)(ext - 1) * ist;
-        max_u += (uint64_t)(ext - 1) * ust;
-    }
-    void jdim(int J, uint64_t xj, uint64_t uj) {
-        p.J = J;
-        p.xj = (uint32_t)xj;
-        p.uj = (uint32_t)uj;
-        both_j = xj != 0 && uj != 0;
-        max_in += (uint64_t)(J - 1) * xj;
-        max_u += (uint64_t)(J - 1) * uj;
-    }
-    void sum(int n, uint64_t xs, uint64_t us) {
-        p.nsum = n;
-        p.xs = (uint32_t)xs;
-        p.us = (uint32_t)us;
-        max_in += (uint64_t)(n - 1) * xs;
-        max_u += (uint64_t)(n - 1) * us;
-    }
-    // host-side bounds check (elements available from each base pointer)
-    bool fits(uint64_t in_avail, uint64_t u_avail, uint64_t out_avail) const {
-        const uint64_t total = outer * (uint64_t)p.J;
-        return p.nd <= MP_MAXD && p.J >= 1 && p.J <= VM_MAXJ && p.nsum >= 1 && p.nsum <= VM_MAXJ && !both_j &&
-               total < (1ull << 31) && max_in < in_avail && max_in < (1ull << 32) && max_u < u_avail &&
-               total <= out_avail;
-    }
-    const VecModeParams &done() {
-        p.outer_total = (uint32_t)outer;
-        return p;
-    }
-};
-
 // Isometry expand-product description (see ExpandParams).
 struct XP {
     ExpandParams p{};

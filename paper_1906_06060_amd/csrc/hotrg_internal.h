@@ -33,37 +33,6 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv &f) {
     return (__umulhi(n, f.mul) + n) >> f.shift;
 }
 
-// A strided multi-index map: output element o (row-major over ext[0..nd-1])
-// reads the input at sum_k coord_k * in_st[k] and a small matrix U at
-// sum_k coord_k * u_st[k]; the contracted index i adds i * in_sum_st and
-// i * u_sum_st.  All offsets are element offsets below 2^32.
-constexpr int MP_MAXD = 10;
-struct ModeParams {
-    int nd;
-    int nsum;
-    uint32_t total;
-    uint32_t in_sum_st, u_sum_st;
-    FastDiv ext[MP_MAXD];
-    uint32_t in_st[MP_MAXD];
-    uint32_t u_st[MP_MAXD];
-};
-
-// Vectorised isometry product: each thread owns one `outer` index and writes
-// the J consecutive outputs of the innermost output dimension j:
-//   out[o * J + j] = sum_{i < nsum} U[u(o) + i us + j uj] * in[x(o) + i xs + j xj].
-// Either the isometry (uj != 0, xj == 0: the input run is loaded once) or the
-// input (xj != 0, uj == 0: the isometry column is loaded once) carries j.
-constexpr int VM_MAXJ = 16;
-struct VecModeParams {
-    int nd;  // outer dims
-    int J, nsum;
-    uint32_t outer_total;
-    uint32_t xs, us, xj, uj;
-    FastDiv ext[MP_MAXD];
-    uint32_t in_st[MP_MAXD];
-    uint32_t u_st[MP_MAXD];
-};
-
 // Isometry product with wave-uniform isometry addresses.  A thread owns one
 // index of the `thread` dims (which address the input and the output) and
 // loops over up to two `loop` dims that only address the isometry and the
@@ -133,13 +102,6 @@ struct PermParams {
 void launch_init_site(double *T, double *S, double w00, double w01, double w10, double w11,
                       double v_up, double v_dn, hipStream_t s);
 void launch_permute(const PermParams &p, const double *in, double *out, double scale, hipStream_t s);
-void launch_mode_product(const ModeParams &p, const double *in, const double *U, double *out,
-                         hipStream_t s);
-void launch_mode_product_split(const ModeParams &p, const double *in, const double *U,
-                               uint16_t *hi, uint16_t *lo, hipStream_t s);
-// out (FP64) or hi/lo (bf16 split) when hi != nullptr
-void launch_mode_product_vec(const VecModeParams &p, const double *in, const double *U, double *out,
-                             uint16_t *hi, uint16_t *lo, hipStream_t s);
 // out (FP64) or hi/lo (bf16 split) when hi != nullptr
 void launch_iso_expand(const ExpandParams &p, const double *in, const double *U, double *out,
                        uint16_t *hi, uint16_t *lo, hipStream_t s);

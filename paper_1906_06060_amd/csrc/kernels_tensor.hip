@@ -70,41 +70,6 @@ void launch_permute(const PermParams &p, const double *in, double *out, double s
     permute_kernel<<<grid_for(p.total), kThreads, 0, s>>>(p, in, out, scale);
 }
 
-// ---------------------------------------------------------------------------
-// Isometry (mode) product: out[o] = sum_i U[u(o) + i us] in[x(o) + i xs].
-// Consecutive threads produce consecutive outputs (coalesced stores); the
-// isometry is tiny and stays in L1/L2.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void mp_offsets(const ModeParams &p, uint32_t o, uint32_t &ib, uint32_t &ub) {
-    uint32_t rem = o;
-    ib = 0;
-    ub = 0;
-    for (int k = p.nd - 1; k >= 0; --k) {
-        uint32_t q = fast_div(rem, p.ext[k]);
-        uint32_t c = rem - q * p.ext[k].d;
-        ib += c * p.in_st[k];
-        ub += c * p.u_st[k];
-        rem = q;
-    }
-}
-
-__device__ __forceinline__ double mp_sum(const ModeParams &p, const double *__restrict__ in,
-                                         const double *__restrict__ U, uint32_t ib, uint32_t ub) {
-    double acc = 0.0;
-    for (int i = 0; i < p.nsum; ++i) acc = fma(U[ub + i * p.u_sum_st], in[ib + i * p.in_sum_st], acc);
-    return acc;
-}
-
-__global__ void __launch_bounds__(kThreads) mode_product_kernel(ModeParams p, const double *__restrict__ in,
-                                                                const double *__restrict__ U,
-                                                                double *__restrict__ out) {
-    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.total; o += gridDim.x * blockDim.x) {
-        uint32_t ib, ub;
-        mp_offsets(p, o, ib, ub);
-        out[o] = mp_sum(p, in, U, ib, ub);
-    }
-}
-
 // bf16 round-to-nearest-even of a float (finite inputs), raw bits.
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
     uint32_t u = __float_as_uint(f);
@@ -113,76 +78,6 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 }
 __device__ __forceinline__ double bf16_value(uint16_t b) {
     return (double)__uint_as_float(((uint32_t)b) << 16);
-}
-
-__global__ void __launch_bounds__(kThreads) mode_product_split_kernel(ModeParams p, const double *__restrict__ in,
-                                                                      const double *__restrict__ U,
-                                                                      uint16_t *__restrict__ hi,
-                                                                      uint16_t *__restrict__ lo) {
-    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.total; o += gridDim.x * blockDim.x) {
-        uint32_t ib, ub;
-        mp_offsets(p, o, ib, ub);
-        double a = mp_sum(p, in, U, ib, ub);
-        uint16_t h = bf16_bits((float)a);
-        uint16_t l = bf16_bits((float)(a - bf16_value(h)));
-        hi[o] = h;
-        lo[o] = l;
-    }
-}
-
-template <bool U_CARRIES_J, bool SPLIT>
-__global__ void __launch_bounds__(kThreads) mode_product_vec_kernel(VecModeParams p, const double *__restrict__ in,
-                                                                    const double *__restrict__ U,
-                                                                    double *__restrict__ out,
-                                                                    uint16_t *__restrict__ hi,
-                                                                    uint16_t *__restrict__ lo) {
-    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.outer_total; o += gridDim.x * blockDim.x) {
-        uint32_t rem = o, ib = 0, ub = 0;
-        for (int k = p.nd - 1; k >= 0; --k) {
-            uint32_t q = fast_div(rem, p.ext[k]);
-            uint32_t c = rem - q * p.ext[k].d;
-            ib += c * p.in_st[k];
-            ub += c * p.u_st[k];
-            rem = q;
-        }
-        double v[VM_MAXJ];  // the operand that does not depend on j
-#pragma unroll
-        for (int i = 0; i < VM_MAXJ; ++i)
-            v[i] = i < p.nsum ? (U_CARRIES_J ? in[ib + i * p.xs] : U[ub + i * p.us]) : 0.0;
-        const uint32_t ob = o * (uint32_t)p.J;
-#pragma unroll
-        for (int j = 0; j < VM_MAXJ; ++j) {
-            if (j >= p.J) break;
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < VM_MAXJ; ++i) {
-                if (i >= p.nsum) break;
-                double w = U_CARRIES_J ? U[ub + i * p.us + j * p.uj] : in[ib + i * p.xs + j * p.xj];
-                acc = fma(w, v[i], acc);
-            }
-            if (SPLIT) {
-                uint16_t h = bf16_bits((float)acc);
-                hi[ob + j] = h;
-                lo[ob + j] = bf16_bits((float)(acc - bf16_value(h)));
-            } else {
-                out[ob + j] = acc;
-            }
-        }
-    }
-}
-
-void launch_mode_product_vec(const VecModeParams &p, const double *in, const double *U, double *out, uint16_t *hi,
-                             uint16_t *lo, hipStream_t s) {
-    if (p.outer_total == 0) return;
-    const int g = grid_for(p.outer_total);
-    const bool uj = p.uj != 0;
-    if (hi) {
-        if (uj) mode_product_vec_kernel<true, true><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
-        else mode_product_vec_kernel<false, true><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
-    } else {
-        if (uj) mode_product_vec_kernel<true, false><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
-        else mode_product_vec_kernel<false, false><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
-    }
 }
 
 // row-major operand offset -> packed GEMM layout (identity when not packed)
@@ -538,17 +433,6 @@ void launch_iso_expand(const ExpandParams &pin, const double *in, const double *
         if (run) iso_expand_kernel<false, true><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
         else iso_expand_kernel<false, false><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
     }
-}
-
-void launch_mode_product(const ModeParams &p, const double *in, const double *U, double *out, hipStream_t s) {
-    if (p.total == 0) return;
-    mode_product_kernel<<<grid_for(p.total), kThreads, 0, s>>>(p, in, U, out);
-}
-
-void launch_mode_product_split(const ModeParams &p, const double *in, const double *U, uint16_t *hi,
-                               uint16_t *lo, hipStream_t s) {
-    if (p.total == 0) return;
-    mode_product_split_kernel<<<grid_for(p.total), kThreads, 0, s>>>(p, in, U, hi, lo);
 }
 
 // ---------------------------------------------------------------------------
