@@ -23,6 +23,10 @@ sample  : single entries / row blocks of one coarse-graining step computed
 tangent : forward-mode derivative of ln Z / N through the whole flow
           (including the eigenvector derivative), independent of any
           reverse-mode code.
+tc      : T_c(Dcut) by bisection on the settled X^(n) of pure-tensor flows
+          (Sec. 3).
+jump    : energy and magnetisation jumps at T_c from two-sided straight
+          lines, m taken to zero field from two small fields (Sec. 3).
 
 Pins: every function is pinned by tests in `tests/test_oracle_*.py` against
 values fixed by the paper or by mathematics.  Functions without such a pin say
