@@ -267,6 +267,23 @@ def test_flow_c1_dcut4_matches_oracle(H):
         assert g["m_imp"] == 0.0          # Z2 kept exactly at h = 0
 
 
+def test_flow_dcut4_matches_stored_values(H):
+    # the same flow against tests/golden/dcut4_beta01497_16steps.json (written
+    # from the oracle by tests/golden/make_golden.py)
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "dcut4_beta01497_16steps.json")))
+    got = H.flow(gold["beta"], gold["h"], gold["dcut"], len(gold["steps"]))
+    for g, w in zip(got, gold["steps"]):
+        assert list(g["dims"]) == w["dims"]
+        assert g["last_cn"] == pytest.approx(w["c_n"], rel=1e-10)
+        assert g["lnz_per_site"] == pytest.approx(w["lnz_per_site"], rel=1e-10)
+        assert g["e_imp"] == pytest.approx(w["e_imp"], abs=1e-8)
+        assert g["X"] == pytest.approx(w["X"], abs=1e-8)
+        assert g["m_imp"] == w["m_imp"] == 0.0
+
+
 @pytest.mark.parametrize("beta,h", [(0.16, 0.01), (0.12, 1e-4)])
 def test_flow_with_field_matches_oracle(H, beta, h):
     _compare_flow(H, beta, h, 4, 10)

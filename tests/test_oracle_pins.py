@@ -356,3 +356,21 @@ def test_d2_two_sided_lines_match_onsager_lines():
     m = [X.onsager_magnetization(1.0 / T) if T < t_c else 0.0 for T in temps]
     assert r["delta_e"] == pytest.approx(at_tc(temps[2:], e[2:]) - at_tc(temps[:2], e[:2]), abs=5e-3)
     assert r["delta_m"] == pytest.approx(at_tc(temps[:2], m[:2]) - at_tc(temps[2:], m[2:]), abs=1e-4)
+
+
+# ---------------------------------------------------------------------------
+# Regression guard (not a pin): the oracle still reproduces the stored flow
+# of tests/golden/, which tests/golden/make_golden.py wrote from it.
+# ---------------------------------------------------------------------------
+def test_oracle_reproduces_stored_dcut4_flow():
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "dcut4_beta01497_16steps.json")))
+    f = H.run(gold["beta"], gold["h"], gold["dcut"], 4, len(gold["steps"]))
+    for r, w in zip(f.records, gold["steps"]):
+        assert list(r.dims) == w["dims"]
+        assert r.lnz_per_site == pytest.approx(w["lnz_per_site"], rel=1e-12)
+        assert r.e_imp == pytest.approx(w["e_imp"], abs=1e-10)
+        assert r.X == pytest.approx(w["X"], abs=1e-10)
+        assert r.m_imp == w["m_imp"]
