@@ -18,11 +18,15 @@
  *   - Every call returns an int status (HOTRG_OK = 0 or a negative code);
  *     no C++ exception crosses the ABI.  hotrg_last_error() gives a
  *     thread-local message for the last failure on the calling thread.
- *   - Ownership: the context owns every device buffer it allocates
- *     (hipMalloc); hotrg_free releases them.  Host pointers passed in are
- *     only read (or written, for outputs) during the call.
- *   - After HOTRG_EDEVICE or HOTRG_ENUMERIC the context is marked failed:
- *     every later call except hotrg_free returns HOTRG_ESTATE.
+ *   - Ownership: the context owns every device buffer it holds; they come
+ *     from the caller's allocator when hotrg_config.alloc / free are given
+ *     (a framework's caching allocator, for instance), else from hipMalloc,
+ *     and hotrg_free returns them.  Host pointers passed in are only read
+ *     (or written, for outputs) during the call.
+ *   - After HOTRG_EDEVICE or HOTRG_ENUMERIC, and after any failure inside a
+ *     step that got past its argument checks (HOTRG_ENOMEM included), the
+ *     context is marked failed: every later call except hotrg_free returns
+ *     HOTRG_ESTATE.  The one exception is documented at hotrg_backward.
  */
 #ifndef HOTRG_H
 #define HOTRG_H
@@ -37,10 +41,12 @@ extern "C" {
 enum {
     HOTRG_OK = 0,
     HOTRG_EINVAL = -1,   /* bad argument (range, NULL pointer, axis not in 0..3) */
-    HOTRG_ENOMEM = -2,   /* device allocation failed or the plan exceeds the budget */
+    HOTRG_ENOMEM = -2,   /* device allocation failed (allocator returned NULL) or mem_budget exceeded */
     HOTRG_EDEVICE = -3,  /* a HIP call failed */
     HOTRG_ESTATE = -4,   /* call not valid in the current state */
-    HOTRG_ENUMERIC = -5  /* norm or trace not finite and positive (Tr <= 0 signals breakdown) */
+    HOTRG_ENUMERIC = -5  /* norm or trace not finite and positive (Tr <= 0 signals breakdown),
+                            eigensolver not converged, non-finite derivative, or a
+                            derivative through a cut with no spectral gap */
 };
 
 enum { HOTRG_FP64 = 0, HOTRG_BF16X3 = 1 };
@@ -58,6 +64,20 @@ typedef struct {
     size_t slice_budget;  /* operand bytes of one K slice above which the contraction
                              slices also fix the b1' index (one value per slice); 0 ->
                              only where a slice would exceed 2^31 elements per tensor */
+    int eig_max_sweeps;   /* sweep cap of the Jacobi eigensolver (0 -> 40, at most 1000); a
+                             solve that reaches it with a squared off-diagonal norm above
+                             1e-24 of the total fails the step with HOTRG_ENUMERIC */
+    /* Device memory: when alloc is set, every buffer of the context comes from
+     * alloc(bytes, alloc_ctx) (bytes a multiple of 256; the result must be device
+     * memory aligned to 256 bytes, usable on `stream`) and goes back through
+     * free(ptr, alloc_ctx) after the stream has finished with it.  alloc and free
+     * are given together or not at all; NULL -> hipMalloc / hipFree.  A NULL
+     * return from alloc gives HOTRG_ENOMEM. */
+    void *(*alloc)(size_t bytes, void *alloc_ctx);
+    void (*free)(void *ptr, void *alloc_ctx);
+    void *alloc_ctx;
+    size_t mem_budget;    /* most device bytes the context may hold at once; an allocation
+                             that would exceed it fails with HOTRG_ENOMEM; 0 -> no limit */
 } hotrg_config;
 
 /* Set up the one-site state of Eqs. (2.2) and (2.6) with bond dimension 2:
@@ -102,6 +122,8 @@ typedef struct {
     int flagged;        /* 1 if a cut stayed inside a degenerate multiplet (no gap above tau) */
     double last_cn;     /* c_n of the last step (Frobenius norm before normalisation) */
     size_t device_bytes;/* device memory held by the context */
+    int eig_sweeps;     /* most Jacobi sweeps one eigendecomposition of the last step took */
+    double eig_residual;/* largest squared off-diagonal / total norm those solves left */
 } hotrg_obs;
 
 /* Observables at the current step (impurity ratios need impurities = 1).
@@ -109,11 +131,22 @@ typedef struct {
  * with hotrg_set_state): lnz_per_site is then NaN. */
 int hotrg_observables(hotrg_ctx *ctx, hotrg_obs *out);
 
-/* Per-site derivatives of ln Z / N at the current step by reverse-mode
- * differentiation of the whole chain (needs keep_checkpoints = 1):
+/* Per-site derivatives of ln Z / N at the current step (Sec. 2: the expectation
+ * values follow from derivatives of ln Z, the route the paper sets beside the
+ * impurity method and compares with it in Sec. 3), computed by reverse-mode
+ * differentiation of the whole coarse-graining chain through the
+ * eigendecomposition-derived isometries (needs keep_checkpoints = 1 and a flow
+ * that started at hotrg_init):
  *   *dlnz_dbeta = d(lnZ/N)/d beta  (energy per site e = -dlnz_dbeta),
  *   *dlnz_dh    = d(lnZ/N)/d h     (magnetisation m = dlnz_dh / beta).
- * beta must exceed 1e-3 (the chain rule through sqrt(sinh b) diverges at 0). */
+ * The c_n of Eq. (2.5)'s bookkeeping are held fixed (ln Z is exactly invariant
+ * to them); an isometry's derivative keeps kept x discarded eigenvector pairs,
+ * with weights 1 / (lam_i - lam_j).  Errors: HOTRG_EINVAL for beta <= 1e-3 (the
+ * chain rule through sqrt(sinh b) diverges at 0); HOTRG_ESTATE without
+ * checkpoints or after hotrg_set_state; HOTRG_ENUMERIC when a step's cut had no
+ * spectral gap above tau (hotrg_obs.flagged; that derivative is undefined) --
+ * returned before any device work and without marking the context failed -- or
+ * when the result is not finite (context marked failed). */
 int hotrg_backward(hotrg_ctx *ctx, double *dlnz_dbeta, double *dlnz_dh);
 
 void hotrg_free(hotrg_ctx *ctx);
@@ -134,13 +167,23 @@ int hotrg_get_tensor(hotrg_ctx *ctx, int which, double *out, size_t count);
 int hotrg_set_state(hotrg_ctx *ctx, const int dims[4], const double *T, const double *Sm,
                     const double *Se, int n, double lnz_acc);
 
+/* The environment / eigendecomposition / cut stage of a step along `axis`
+ * (Sec. 2; squeezed HOSVD environments, FP64 eigh, truncation to k <= dcut)
+ * on the current state, without the contraction: the state and the step count
+ * are unchanged.  Afterwards hotrg_get_isometry, hotrg_get_spectrum and the
+ * last_side / last_k / last_eps / min_cut_gap / flagged / eig_* fields of
+ * hotrg_observables describe this stage.  Used to check the stage on
+ * identical inputs at sizes where a whole step is long. */
+int hotrg_truncate(hotrg_ctx *ctx, int axis);
+
 /* Step with caller-given isometries instead of the environment/eigh stage:
  * U[q] (host, row-major D_q^2 x k[q]) for the three transverse axes q != axis
  * (U[axis] is ignored).  Used to check the contraction on identical inputs. */
 int hotrg_step_with_isometries(hotrg_ctx *ctx, int axis, const double *const U[4], const int k[4]);
 
-/* Host copy of the isometry of axis `q` used in the last step (row-major,
- * rows*cols doubles) and of the descending spectrum of its (q, side) env. */
+/* Host copy of the isometry of axis `q` of the last step or hotrg_truncate
+ * call (row-major, rows*cols doubles) and of the descending spectrum of its
+ * (q, side) environment. */
 int hotrg_get_isometry(hotrg_ctx *ctx, int q, double *out, size_t count, int *rows, int *cols);
 int hotrg_get_spectrum(hotrg_ctx *ctx, int q, int side, double *out, size_t count, int *len);
 

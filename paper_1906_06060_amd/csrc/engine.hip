@@ -52,6 +52,9 @@ struct DevBuf {
 };
 
 constexpr double kSideTie = 1e-11;
+// an eigensolve that reaches the sweep cap still counts as converged when the
+// squared off-diagonal norm it leaves is below this fraction of the total
+constexpr double kEigResidOk = 1e-24;
 constexpr int kMaxEnvN = 144;
 
 }  // namespace
@@ -81,6 +84,7 @@ struct hotrg_ctx {
     double *V = nullptr;     // 6 * 144^2
     double *jwork = nullptr; // 2 * 2 * 145^2
     int *sweeps = nullptr;
+    double *resid = nullptr;
     double *U[3] = {nullptr, nullptr, nullptr};  // chosen isometries, 144^2 each, row-major n x k
     double *partials = nullptr;                   // 1024
     double *scal = nullptr;                       // 64
@@ -97,6 +101,9 @@ struct hotrg_ctx {
     double min_gap = INFINITY;
     int flagged = 0;
     double last_cn = 0;
+    int iso_axis = -1;       // axis of the step the current isometries belong to
+    int eig_sweeps = 0;      // most Jacobi sweeps of one solve in the last step
+    double eig_resid = 0;    // largest off-diagonal / total squared norm left by those solves
 
     // GEMM timing
     std::vector<hipEvent_t> ev_pool;
@@ -121,6 +128,7 @@ struct hotrg_ctx {
         int n[3];         // n = D^2 of each transverse axis
         int side[3];      // environment side the isometry came from
         bool trunc[3];    // isometry from an eigendecomposition (else constant)
+        bool flagged[3];  // the cut stayed inside a degenerate multiplet (no gap above tau)
         double c;         // c_n of the step
         double *T;        // state before the step
         double *U[3];     // n x k
@@ -152,19 +160,51 @@ namespace {
         if (rc_ != HOTRG_OK) return rc_; \
     } while (0)
 
+// Every device buffer of a context comes from here: the caller's allocator
+// (hotrg_config.alloc / free, e.g. a framework's caching allocator) when one
+// is given, else hipMalloc.  mem_budget caps the bytes held at once.
 int dev_alloc(hotrg_ctx *c, void **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return set_err(HOTRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
-                                         hipGetErrorString(e));
+    bytes = (bytes + 255) / 256 * 256;
+    if (c->cfg.mem_budget > 0 && c->device_bytes + bytes > c->cfg.mem_budget)
+        return set_err(HOTRG_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes would exceed mem_budget (" +
+                                         std::to_string(c->cfg.mem_budget) + " bytes, " +
+                                         std::to_string(c->device_bytes) + " held)");
+    if (c->cfg.alloc) {
+        *p = c->cfg.alloc(bytes, c->cfg.alloc_ctx);
+        if (!*p) return set_err(HOTRG_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return set_err(HOTRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                             hipGetErrorString(e));
+        }
     }
     c->owned.push_back(DevBuf{*p, bytes});
     c->device_bytes += bytes;
     return HOTRG_OK;
+}
+
+void release(hotrg_ctx *c, void *p) {
+    if (c->cfg.free) c->cfg.free(p, c->cfg.alloc_ctx);
+    else (void)hipFree(p);
+}
+
+// Returns one buffer obtained from dev_alloc (the stream must be idle with
+// respect to it).  Unknown or null pointers are ignored.
+void dev_free(hotrg_ctx *c, void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < c->owned.size(); ++i)
+        if (c->owned[i].p == p) {
+            c->device_bytes -= c->owned[i].bytes;
+            release(c, p);
+            c->owned[i] = c->owned.back();
+            c->owned.pop_back();
+            return;
+        }
 }
 
 template <typename T>
@@ -176,13 +216,7 @@ int ensure(hotrg_ctx *c, DevBuf &b, size_t bytes) {
     if (b.bytes >= bytes) return HOTRG_OK;
     if (b.p) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        for (auto &o : c->owned)
-            if (o.p == b.p) {
-                c->device_bytes -= o.bytes;
-                o.p = nullptr;
-                o.bytes = 0;
-            }
-        (void)hipFree(b.p);
+        dev_free(c, b.p);
         b.p = nullptr;
         b.bytes = 0;
     }
@@ -449,6 +483,9 @@ int isometries(hotrg_ctx *c, const double *T, const uint64_t lst[8], const int l
     }
     c->min_gap = INFINITY;
     c->flagged = 0;
+    c->eig_sweeps = 0;
+    c->eig_resid = 0;
+    c->iso_axis = mu;
     for (int i = 0; i < 3; ++i) {
         const int D = ldim[2 * i];
         const int nmat = D * D;
@@ -472,12 +509,30 @@ int isometries(hotrg_ctx *c, const double *T, const uint64_t lst[8], const int l
         }
         // both sides share n, so they go in one launch; matrices packed at stride n*n
         launch_jacobi_eigh(Eb, nmat, 2, c->lam + (size_t)2 * i * kMaxEnvN, c->V + (size_t)2 * i * kMaxEnvN * kMaxEnvN,
-                           c->jwork, c->sweeps, c->stream);
+                           c->jwork, c->sweeps, c->resid, c->cfg.eig_max_sweeps, c->stream);
         TRY(check_launch(c, "environment / eigh"));
         std::vector<double> lam(2 * (size_t)nmat);
+        int sw[2] = {0, 0};
+        double rs[2] = {0, 0};
         HIP_TRY(c, hipMemcpyAsync(lam.data(), c->lam + (size_t)2 * i * kMaxEnvN, sizeof(double) * 2 * nmat,
                                   hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(sw, c->sweeps, sizeof(sw), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(rs, c->resid, sizeof(rs), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int side = 0; side < 2; ++side) {
+            c->eig_sweeps = std::max(c->eig_sweeps, sw[side]);
+            c->eig_resid = std::max(c->eig_resid, rs[side]);
+            // the sweep cap was reached with an off-diagonal part above the
+            // rounding level: the eigenvectors are not converged
+            if (sw[side] >= c->cfg.eig_max_sweeps && !(rs[side] <= kEigResidOk)) {
+                c->failed = true;
+                return set_err(HOTRG_ENUMERIC,
+                               "eigensolver did not converge in " + std::to_string(c->cfg.eig_max_sweeps) +
+                                   " sweeps (environment of axis " + std::to_string(q) + ", side " +
+                                   std::to_string(side) + ", n = " + std::to_string(nmat) +
+                                   ", off-diagonal / total squared norm " + std::to_string(rs[side]) + ")");
+            }
+        }
         Decision db = choose_cut(lam.data(), nmat, c->dcut, c->cfg.tau_deg);
         Decision df = choose_cut(lam.data() + nmat, nmat, c->dcut, c->cfg.tau_deg);
         double eb = discarded(lam.data(), nmat, db.k), ef = discarded(lam.data() + nmat, nmat, df.k);
@@ -500,7 +555,6 @@ int isometries(hotrg_ctx *c, const double *T, const uint64_t lst[8], const int l
         c->Urows[q] = nmat;
         c->Ucols[q] = d.k;
     }
-    (void)mu;
     return HOTRG_OK;
 }
 
@@ -795,11 +849,33 @@ void transverse_of(int mu, int tv[3]) {
         if (q != mu) tv[j++] = q;
 }
 
+void free_checkpoint(hotrg_ctx *c, hotrg_ctx::Checkpoint &cp) {
+    dev_free(c, cp.T);
+    cp.T = nullptr;
+    for (int i = 0; i < 3; ++i) {
+        dev_free(c, cp.U[i]);
+        dev_free(c, cp.lam[i]);
+        dev_free(c, cp.V[i]);
+        cp.U[i] = cp.lam[i] = cp.V[i] = nullptr;
+    }
+}
+
+// Drops every stored checkpoint and returns its memory (waits for the stream,
+// which may still read them).
+int clear_checkpoints(hotrg_ctx *c) {
+    if (c->ckpts.empty()) return HOTRG_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto &cp : c->ckpts) free_checkpoint(c, cp);
+    c->ckpts.clear();
+    return HOTRG_OK;
+}
+
 // Copy of everything the reverse pass needs from the step about to run: the
 // state T, the isometries, and (for truncated axes) the chosen side's full
 // eigendecomposition.  Isometries given by the caller count as constants.
-int save_checkpoint(hotrg_ctx *c, int axis, const int tv[3], const int k[3], bool given_u) {
-    hotrg_ctx::Checkpoint cp{};
+// Built in c->pending; on failure the partial copy is freed again.
+int save_checkpoint_into(hotrg_ctx *c, hotrg_ctx::Checkpoint &cp, int axis, const int tv[3], const int k[3],
+                         bool given_u) {
     for (int q = 0; q < 4; ++q) cp.dims[q] = c->dims[q];
     cp.axis = axis;
     const size_t ts = tensor_size(c->dims);
@@ -813,10 +889,10 @@ int save_checkpoint(hotrg_ctx *c, int axis, const int tv[3], const int k[3], boo
         cp.n[i] = nmat;
         cp.trunc[i] = !given_u && c->dec[q].truncated;
         cp.side[i] = cp.trunc[i] ? c->dec[q].side : 0;
+        cp.flagged[i] = cp.trunc[i] && c->dec[q].flagged;
         TRY(alloc_n(c, &cp.U[i], (size_t)nmat * k[i]));
         HIP_TRY(c, hipMemcpyAsync(cp.U[i], c->U[i], sizeof(double) * nmat * k[i], hipMemcpyDeviceToDevice,
                                   c->stream));
-        cp.lam[i] = cp.V[i] = nullptr;
         if (cp.trunc[i]) {
             const int side = c->dec[q].side;
             TRY(alloc_n(c, &cp.lam[i], (size_t)nmat));
@@ -828,8 +904,17 @@ int save_checkpoint(hotrg_ctx *c, int axis, const int tv[3], const int k[3], boo
                                       sizeof(double) * nmat * nmat, hipMemcpyDeviceToDevice, c->stream));
         }
     }
-    c->pending = cp;
     return HOTRG_OK;
+}
+
+int save_checkpoint(hotrg_ctx *c, int axis, const int tv[3], const int k[3], bool given_u) {
+    c->pending = hotrg_ctx::Checkpoint{};
+    int rc = save_checkpoint_into(c, c->pending, axis, tv, k, given_u);
+    if (rc != HOTRG_OK) {
+        (void)hipStreamSynchronize(c->stream);
+        free_checkpoint(c, c->pending);
+    }
+    return rc;
 }
 
 // Adds the phase intervals of the last completed step (waits for its end).
@@ -846,6 +931,31 @@ int flush_phases(hotrg_ctx *c) {
     return HOTRG_OK;
 }
 
+int run_step_body(hotrg_ctx *c, int axis, const int tv[3], const int k[3]) {
+    HIP_TRY(c, hipEventRecord(c->ph[1], c->stream));
+    TRY(contract(c, axis, tv, k));
+    HIP_TRY(c, hipEventRecord(c->ph[2], c->stream));
+    TRY(finish_step(c, axis, tv, k));
+    HIP_TRY(c, hipEventRecord(c->ph[3], c->stream));
+    c->ph_pending = true;
+    return HOTRG_OK;
+}
+
+// Local leg numbering of a step along mu: 0..5 the transverse legs
+// (a, a', b, b', c, c'), 6 = mu (backward), 7 = mu' (forward).
+void local_legs(const int D[4], int mu, const int tv[3], uint64_t lst[8], int ldim[8]) {
+    uint64_t cst[8];
+    canon_strides(D, cst);
+    for (int i = 0; i < 3; ++i) {
+        lst[2 * i] = cst[2 * tv[i]];
+        lst[2 * i + 1] = cst[2 * tv[i] + 1];
+        ldim[2 * i] = ldim[2 * i + 1] = D[tv[i]];
+    }
+    lst[6] = cst[2 * mu];
+    lst[7] = cst[2 * mu + 1];
+    ldim[6] = ldim[7] = D[mu];
+}
+
 int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost) {
     if (!c) return set_err(HOTRG_EINVAL, "null context");
     if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
@@ -856,26 +966,24 @@ int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost
     HIP_TRY(c, hipEventRecord(c->ph[0], c->stream));
     int tv[3];
     transverse_of(axis, tv);
-    uint64_t cst[8];
-    canon_strides(c->dims, cst);
     uint64_t lst[8];
     int ldim[8];
-    for (int i = 0; i < 3; ++i) {
-        lst[2 * i] = cst[2 * tv[i]];
-        lst[2 * i + 1] = cst[2 * tv[i] + 1];
-        ldim[2 * i] = ldim[2 * i + 1] = c->dims[tv[i]];
-    }
-    lst[6] = cst[2 * axis];
-    lst[7] = cst[2 * axis + 1];
-    ldim[6] = ldim[7] = c->dims[axis];
+    local_legs(c->dims, axis, tv, lst, ldim);
     int k[3];
     if (Uhost) {
-        for (int q = 0; q < 4; ++q) c->dec[q] = Decision();
         for (int i = 0; i < 3; ++i) {
             int q = tv[i];
             int nmat = c->dims[q] * c->dims[q];
             if (!Uhost[q] || khost[q] < 1 || khost[q] > std::max(c->dcut, 2) || khost[q] > nmat)
                 return set_err(HOTRG_EINVAL, "isometry for a transverse axis missing or k out of range");
+        }
+        for (int q = 0; q < 4; ++q) c->dec[q] = Decision();
+        c->iso_axis = axis;
+        c->eig_sweeps = 0;
+        c->eig_resid = 0;
+        for (int i = 0; i < 3; ++i) {
+            int q = tv[i];
+            int nmat = c->dims[q] * c->dims[q];
             HIP_TRY(c, hipMemcpyAsync(c->U[i], Uhost[q], sizeof(double) * nmat * khost[q], hipMemcpyHostToDevice,
                                       c->stream));
             k[i] = khost[q];
@@ -887,16 +995,25 @@ int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost
     } else {
         TRY(isometries(c, c->state[0], lst, ldim, tv, axis, k));
     }
-    if (c->cfg.keep_checkpoints) TRY(save_checkpoint(c, axis, tv, k, Uhost != nullptr));
-    HIP_TRY(c, hipEventRecord(c->ph[1], c->stream));
-    TRY(contract(c, axis, tv, k));
-    HIP_TRY(c, hipEventRecord(c->ph[2], c->stream));
-    TRY(finish_step(c, axis, tv, k));
-    HIP_TRY(c, hipEventRecord(c->ph[3], c->stream));
-    c->ph_pending = true;
+    int rc = c->cfg.keep_checkpoints ? save_checkpoint(c, axis, tv, k, Uhost != nullptr) : HOTRG_OK;
+    if (rc != HOTRG_OK) {
+        c->failed = true;
+        return rc;
+    }
+    rc = run_step_body(c, axis, tv, k);
+    if (rc != HOTRG_OK) {
+        // a failed step leaves the context failed; its checkpoint copy goes
+        if (c->cfg.keep_checkpoints) {
+            (void)hipStreamSynchronize(c->stream);
+            free_checkpoint(c, c->pending);
+        }
+        c->failed = true;
+        return rc;
+    }
     if (c->cfg.keep_checkpoints) {
         c->pending.c = c->last_cn;
         c->ckpts.push_back(c->pending);
+        c->pending = hotrg_ctx::Checkpoint{};
     }
     return HOTRG_OK;
 }
@@ -1467,6 +1584,15 @@ int backward(hotrg_ctx *c, double *dbeta, double *dh) {
     if (c->ckpt_broken || (int)c->ckpts.size() != c->n)
         return set_err(HOTRG_ESTATE, "checkpoints do not cover the flow from the initial tensor");
     if (!(c->beta > 1e-3)) return set_err(HOTRG_EINVAL, "hotrg_backward needs beta > 1e-3");
+    // a cut inside a degenerate multiplet has no eigenvector derivative
+    // (1 / (lam_i - lam_j) with lam_i = lam_j); refused before any device work
+    for (size_t s = 0; s < c->ckpts.size(); ++s)
+        for (int i = 0; i < 3; ++i)
+            if (c->ckpts[s].flagged[i])
+                return set_err(HOTRG_ENUMERIC, "step " + std::to_string(s + 1) + ", axis " +
+                                                   std::to_string(c->ckpts[s].tv[i]) +
+                                                   ": the cut has no spectral gap above tau, the derivative of "
+                                                   "the isometry is undefined");
     double tr, trm, tre;
     TRY(read_obs(c, &tr, &trm, &tre, nullptr));
     if (!(tr > 0) || !std::isfinite(tr)) {
@@ -1499,6 +1625,10 @@ int backward(hotrg_ctx *c, double *dbeta, double *dh) {
     double out[2];
     HIP_TRY(c, hipMemcpyAsync(out, c->scal, sizeof(out), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+        c->failed = true;
+        return set_err(HOTRG_ENUMERIC, "reverse pass produced a non-finite derivative");
+    }
     *dbeta = out[0];
     *dh = out[1];
     return HOTRG_OK;
@@ -1530,6 +1660,15 @@ int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotr
         return set_err(HOTRG_EINVAL, "unknown precision");
     }
     if (c->cfg.mixed_from_step <= 0) c->cfg.mixed_from_step = 4;
+    if (c->cfg.eig_max_sweeps <= 0) c->cfg.eig_max_sweeps = 40;
+    if (c->cfg.eig_max_sweeps > 1000) {
+        delete c;
+        return set_err(HOTRG_EINVAL, "eig_max_sweeps must be at most 1000");
+    }
+    if ((c->cfg.alloc == nullptr) != (c->cfg.free == nullptr)) {
+        delete c;
+        return set_err(HOTRG_EINVAL, "alloc and free must be given together");
+    }
     if (!(c->cfg.tau_deg > 0)) c->cfg.tau_deg = 1e-12;
     c->stream = (hipStream_t)c->cfg.stream;
     const int Dmax = std::max(dcut, 2);
@@ -1556,6 +1695,7 @@ int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotr
     if ((rc = alloc_n(c, &c->V, 6 * E2))) return fail(rc);
     if ((rc = alloc_n(c, &c->jwork, (size_t)4 * (kMaxEnvN + 1) * (kMaxEnvN + 1)))) return fail(rc);
     if ((rc = alloc_n(c, &c->sweeps, 8))) return fail(rc);
+    if ((rc = alloc_n(c, &c->resid, 8))) return fail(rc);
     for (int i = 0; i < 3; ++i)
         if ((rc = alloc_n(c, &c->U[i], E2))) return fail(rc);
     if ((rc = alloc_n(c, &c->partials, 1024))) return fail(rc);
@@ -1594,6 +1734,21 @@ int hotrg_step(hotrg_ctx *ctx, int axis) { return do_step(ctx, axis, nullptr, nu
 int hotrg_step_with_isometries(hotrg_ctx *ctx, int axis, const double *const U[4], const int k[4]) {
     if (!U || !k) return set_err(HOTRG_EINVAL, "U or k is NULL");
     return do_step(ctx, axis, U, k);
+}
+
+int hotrg_truncate(hotrg_ctx *c, int axis) {
+    if (!c) return set_err(HOTRG_EINVAL, "null context");
+    if (c->failed) return set_err(HOTRG_ESTATE, "context is in a failed state");
+    if (axis < 0 || axis > 3) return set_err(HOTRG_EINVAL, "axis must be 0..3");
+    int tv[3];
+    transverse_of(axis, tv);
+    uint64_t lst[8];
+    int ldim[8];
+    local_legs(c->dims, axis, tv, lst, ldim);
+    int k[3];
+    TRY(isometries(c, c->state[0], lst, ldim, tv, axis, k));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return HOTRG_OK;
 }
 
 int hotrg_lnZ(hotrg_ctx *c, double *lnz) {
@@ -1645,6 +1800,8 @@ int hotrg_observables(hotrg_ctx *c, hotrg_obs *o) {
     }
     o->last_cn = c->last_cn;
     o->device_bytes = c->device_bytes;
+    o->eig_sweeps = c->eig_sweeps;
+    o->eig_residual = c->eig_resid;
     return HOTRG_OK;
 }
 
@@ -1658,7 +1815,7 @@ void hotrg_free(hotrg_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     for (auto &o : c->owned)
-        if (o.p) (void)hipFree(o.p);
+        if (o.p) release(c, o.p);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     for (auto e : c->ph)
         if (e) (void)hipEventDestroy(e);
@@ -1692,6 +1849,9 @@ int hotrg_set_state(hotrg_ctx *c, const int dims[4], const double *T, const doub
         if (dims[q] < 1 || dims[q] > Dmax) return set_err(HOTRG_EINVAL, "dims out of range");
     if (c->cfg.impurities && (!Sm || !Se)) return set_err(HOTRG_EINVAL, "impure tensors required");
     if (n < 0) return set_err(HOTRG_EINVAL, "n must be >= 0");
+    // steps before this state are unknown: the reverse pass cannot reach beta,
+    // h, so the stored checkpoints are dropped (and their memory returned)
+    TRY(clear_checkpoints(c));
     size_t need = tensor_size(dims);
     HIP_TRY(c, hipMemcpyAsync(c->state[0], T, sizeof(double) * need, hipMemcpyHostToDevice, c->stream));
     if (c->cfg.impurities) {
@@ -1704,17 +1864,15 @@ int hotrg_set_state(hotrg_ctx *c, const int dims[4], const double *T, const doub
     c->lnz_acc = lnz_acc;
     c->first_axis = n > 0 ? 0 : -1;
     c->last_axis = -1;
-    // steps before this state are unknown: the reverse pass cannot reach beta, h
-    c->ckpts.clear();
     c->ckpt_broken = true;
     return HOTRG_OK;
 }
 
 int hotrg_get_isometry(hotrg_ctx *c, int q, double *out, size_t count, int *rows, int *cols) {
     if (!c || !out || q < 0 || q > 3) return set_err(HOTRG_EINVAL, "bad argument");
-    if (c->last_axis < 0 || q == c->last_axis) return set_err(HOTRG_ESTATE, "no isometry for this axis");
+    if (c->iso_axis < 0 || q == c->iso_axis) return set_err(HOTRG_ESTATE, "no isometry for this axis");
     int tv[3];
-    transverse_of(c->last_axis, tv);
+    transverse_of(c->iso_axis, tv);
     int i = (q == tv[0]) ? 0 : (q == tv[1] ? 1 : 2);
     size_t need = (size_t)c->Urows[q] * c->Ucols[q];
     if (count < need) return set_err(HOTRG_EINVAL, "output buffer too small");

@@ -145,8 +145,10 @@ void launch_site_dot(const double *Tbar, double wc, double ws, double dwc, doubl
 // Jacobi eigensolver: `count` symmetric n x n matrices (n <= 144) at A + i*n*n,
 // eigenvalues (descending) to lam + i*n, eigenvectors as columns of V + i*n*n
 // (row-major, V[r*n + j] = component r of vector j).  work: 2*count*n*n doubles.
+// At most max_sweeps sweeps; sweeps[i] gets the number taken and resid[i] the
+// squared off-diagonal norm left divided by the squared Frobenius norm.
 void launch_jacobi_eigh(const double *A, int n, int count, double *lam, double *V, double *work,
-                        int *sweeps, hipStream_t s);
+                        int *sweeps, double *resid, int max_sweeps, hipStream_t s);
 
 // C[M x N] (ldc) (+)= A[M x K] (lda) * B[N x K]^T (ldb); FP64 MFMA.
 void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, int K, size_t lda,

@@ -14,7 +14,6 @@ namespace hotrg {
 
 constexpr int JT = 512;          // threads per matrix
 constexpr int J_MAXN = 144;
-constexpr int J_MAXSWEEPS = 40;
 
 __device__ __forceinline__ int rr_player(int pos, int round, int m) {
     // position 0 is fixed, positions 1..m-1 rotate by `round`
@@ -36,7 +35,8 @@ __device__ double jt_block_sum(double v, double *sh) {
 
 __global__ void __launch_bounds__(JT) jacobi_kernel(const double *__restrict__ Ain, int n, double *__restrict__ lam,
                                                     double *__restrict__ Vout, double *__restrict__ work,
-                                                    int *__restrict__ sweeps_out) {
+                                                    int *__restrict__ sweeps_out, double *__restrict__ resid_out,
+                                                    int max_sweeps) {
     __shared__ double cs[J_MAXN / 2 + 1], sn[J_MAXN / 2 + 1];
     __shared__ int pp[J_MAXN / 2 + 1], qq[J_MAXN / 2 + 1];
     __shared__ double red[JT];
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(JT) jacobi_kernel(const double *__restrict__ A
     }
     int sweep = 0;
     if (m >= 2 && fro > 0.0) {
-        for (sweep = 0; sweep < J_MAXSWEEPS; ++sweep) {
+        for (sweep = 0; sweep < max_sweeps; ++sweep) {
             double off = 0.0;
             {
                 double acc = 0.0;
@@ -128,6 +128,18 @@ __global__ void __launch_bounds__(JT) jacobi_kernel(const double *__restrict__ A
             }
         }
     }
+    // squared off-diagonal norm left, relative to the total (the convergence
+    // measure the sweeps test; reported so the host can tell a solve that
+    // stopped at the sweep cap from a converged one)
+    {
+        double acc = 0.0;
+        for (int e = tid; e < m * m; e += JT) {
+            int i = e / m, j = e % m;
+            if (i != j) acc += A[e] * A[e];
+        }
+        const double off = jt_block_sum(acc, red);
+        if (tid == 0 && resid_out) resid_out[mat] = fro > 0.0 ? off / fro : 0.0;
+    }
     // sort eigenvalues descending (stable on ties) and emit columns
     for (int i = tid; i < n; i += JT) dval[i] = A[i * m + i];
     __syncthreads();
@@ -150,9 +162,9 @@ __global__ void __launch_bounds__(JT) jacobi_kernel(const double *__restrict__ A
 }
 
 void launch_jacobi_eigh(const double *A, int n, int count, double *lam, double *V, double *work, int *sweeps,
-                        hipStream_t s) {
+                        double *resid, int max_sweeps, hipStream_t s) {
     if (count <= 0 || n <= 0) return;
-    jacobi_kernel<<<count, JT, 0, s>>>(A, n, lam, V, work, sweeps);
+    jacobi_kernel<<<count, JT, 0, s>>>(A, n, lam, V, work, sweeps, resid, max_sweeps);
 }
 
 }  // namespace hotrg

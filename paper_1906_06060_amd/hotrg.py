@@ -6,9 +6,11 @@ no fallback of any kind -- a missing library raises ``HotrgUnavailable``.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
+import weakref
 
 import numpy as np
 
@@ -22,9 +24,12 @@ FP64, BF16X3 = 0, 1
 EXPORTS = (
     "hotrg_init", "hotrg_init_ex", "hotrg_step", "hotrg_lnZ", "hotrg_observables",
     "hotrg_backward", "hotrg_free", "hotrg_last_error", "hotrg_get_dims", "hotrg_get_tensor",
-    "hotrg_set_state", "hotrg_step_with_isometries", "hotrg_get_isometry", "hotrg_get_spectrum",
-    "hotrg_kernel_stats", "hotrg_reset_stats",
+    "hotrg_set_state", "hotrg_truncate", "hotrg_step_with_isometries", "hotrg_get_isometry",
+    "hotrg_get_spectrum", "hotrg_kernel_stats", "hotrg_reset_stats",
 )
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class HotrgUnavailable(RuntimeError):
@@ -46,6 +51,11 @@ class Config(C.Structure):
         ("tau_deg", C.c_double),
         ("stream", C.c_void_p),
         ("slice_budget", C.c_size_t),
+        ("eig_max_sweeps", C.c_int),
+        ("alloc", ALLOC_FN),
+        ("free", FREE_FN),
+        ("alloc_ctx", C.c_void_p),
+        ("mem_budget", C.c_size_t),
     ]
 
 
@@ -67,6 +77,8 @@ class Obs(C.Structure):
         ("flagged", C.c_int),
         ("last_cn", C.c_double),
         ("device_bytes", C.c_size_t),
+        ("eig_sweeps", C.c_int),
+        ("eig_residual", C.c_double),
     ]
 
     def as_dict(self):
@@ -74,7 +86,8 @@ class Obs(C.Structure):
                     m_imp=self.m_imp, nn_imp=self.nn_imp, e_imp=self.e_imp, X=self.X,
                     last_axis=self.last_axis, last_side=tuple(self.last_side), last_k=tuple(self.last_k),
                     last_eps=tuple(self.last_eps), min_cut_gap=self.min_cut_gap, flagged=self.flagged,
-                    last_cn=self.last_cn, device_bytes=self.device_bytes)
+                    last_cn=self.last_cn, device_bytes=self.device_bytes, eig_sweeps=self.eig_sweeps,
+                    eig_residual=self.eig_residual)
 
 
 _lib = None
@@ -110,6 +123,7 @@ def load(path: str = LIB_PATH):
         "hotrg_get_dims": ([P, ip, ip], C.c_int),
         "hotrg_get_tensor": ([P, C.c_int, dp, C.c_size_t], C.c_int),
         "hotrg_set_state": ([P, ip, dp, dp, dp, C.c_int, C.c_double], C.c_int),
+        "hotrg_truncate": ([P, C.c_int], C.c_int),
         "hotrg_step_with_isometries": ([P, C.c_int, C.POINTER(dp), ip], C.c_int),
         "hotrg_get_isometry": ([P, C.c_int, dp, C.c_size_t, ip, ip], C.c_int),
         "hotrg_get_spectrum": ([P, C.c_int, C.c_int, dp, C.c_size_t, ip], C.c_int),
@@ -145,19 +159,83 @@ def _current_stream():
     return C.c_void_p(0)
 
 
+class TorchAllocator:
+    """Device memory for a context from torch's caching allocator, on the
+    context's stream (the library calls alloc / free through ctypes)."""
+
+    def __init__(self, stream_ptr: int, fail_after: int | None = None):
+        import torch
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = int(stream_ptr or 0)
+        self.fail_after = fail_after      # tests: NULL from the (fail_after + 1)-th request on
+        self.calls = 0
+        self.live = {}
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _ctx):
+        self.calls += 1
+        if self.fail_after is not None and self.calls > self.fail_after:
+            return None
+        try:
+            p = self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except Exception:
+            return None
+        self.live[p] = int(nbytes)
+        return p
+
+    def _free(self, ptr, _ctx):
+        if ptr:
+            self.live.pop(ptr, None)
+            self.torch.cuda.caching_allocator_delete(ptr)
+
+    @property
+    def bytes_held(self) -> int:
+        return sum(self.live.values())
+
+
+_live_contexts = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    # free every context while the interpreter (and torch) can still serve
+    # the allocator callbacks
+    for ctx in list(_live_contexts):
+        try:
+            ctx.close()
+        except Exception:
+            pass
+
+
 class Context:
-    """One HOTRG coarse-graining state on the GPU (hotrg_ctx)."""
+    """One HOTRG coarse-graining state on the GPU (hotrg_ctx).
+
+    allocator="torch" (default when torch sees a GPU): the context's device
+    buffers come from torch's caching allocator; "hip": from hipMalloc inside
+    the library; or a TorchAllocator instance."""
 
     def __init__(self, beta: float, h: float, dcut: int, precision: int = FP64, impurities: bool = True,
                  keep_checkpoints: bool = False, mixed_from_step: int = 0, tau_deg: float = 0.0, stream=None,
-                 slice_budget: int = 0):
+                 slice_budget: int = 0, eig_max_sweeps: int = 0, mem_budget: int = 0, allocator="torch"):
         lib = load()
-        cfg = Config(precision, int(impurities), int(keep_checkpoints), mixed_from_step, tau_deg,
-                     stream if stream is not None else _current_stream(), slice_budget)
         self._h = C.c_void_p()
+        stream = stream if stream is not None else _current_stream()
+        if allocator == "torch":
+            allocator = TorchAllocator(stream.value if isinstance(stream, C.c_void_p) else stream)
+        elif allocator == "hip":
+            allocator = None
+        self.allocator = allocator
+        cfg = Config(precision, int(impurities), int(keep_checkpoints), mixed_from_step, tau_deg, stream,
+                     slice_budget, eig_max_sweeps)
+        if allocator is not None:
+            cfg.alloc, cfg.free = allocator.alloc_fn, allocator.free_fn
+        cfg.mem_budget = mem_budget
         self.beta, self.h, self.dcut = beta, h, dcut
         self.impurities = impurities
         _check(lib.hotrg_init_ex(beta, h, dcut, C.byref(cfg), C.byref(self._h)))
+        _live_contexts.add(self)
 
     def close(self):
         if self._h:
@@ -178,6 +256,10 @@ class Context:
 
     def step(self, axis: int):
         _check(_lib.hotrg_step(self._h, axis))
+
+    def truncate(self, axis: int):
+        """Environment / eigh / cut stage of a step along `axis` only (state unchanged)."""
+        _check(_lib.hotrg_truncate(self._h, axis))
 
     def step_with_isometries(self, axis: int, Us: dict):
         arrs = [np.ascontiguousarray(Us[q], dtype=np.float64) if q in Us else None for q in range(4)]
@@ -225,13 +307,13 @@ class Context:
                                     _dptr(Se) if Se is not None else null, n, lnz_acc))
 
     def isometry(self, q: int) -> np.ndarray:
-        buf = np.empty(144 * 144)
+        buf = np.empty(256 * 256)
         r, c = C.c_int(), C.c_int()
         _check(_lib.hotrg_get_isometry(self._h, q, _dptr(buf), buf.size, C.byref(r), C.byref(c)))
         return buf[: r.value * c.value].reshape(r.value, c.value).copy()
 
     def spectrum(self, q: int, side: int) -> np.ndarray:
-        buf = np.empty(144)
+        buf = np.empty(256)
         n = C.c_int()
         _check(_lib.hotrg_get_spectrum(self._h, q, side, _dptr(buf), buf.size, C.byref(n)))
         return buf[: n.value].copy()

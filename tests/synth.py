@@ -19,10 +19,17 @@ def z2_tensor(dims, seed=SEED, odd=False, dtype=np.float64):
         shape += [D, D]
     rng = np.random.default_rng(seed)
     T = rng.standard_normal(shape)
-    par = np.indices(shape).sum(axis=0) % 2
+    # parity of the index sum, accumulated leg by leg with broadcasting (one
+    # int8 array: no index grids of the full shape at Dcut = 12)
+    par = np.zeros(shape, dtype=np.int8)
+    for leg, D in enumerate(shape):
+        view = [1] * len(shape)
+        view[leg] = D
+        par ^= (np.arange(D, dtype=np.int8) % 2).reshape(view)
     T[par != (1 if odd else 0)] = 0.0
+    del par
     T /= np.linalg.norm(T)
-    return T.astype(dtype)
+    return T.astype(dtype, copy=False)
 
 
 def isometry(n, k, seed=SEED + 1):

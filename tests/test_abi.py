@@ -48,3 +48,57 @@ def test_null_handles_are_rejected():
     assert lib.hotrg_lnZ(None, C.byref(v)) == hotrg.EINVAL
     assert lib.hotrg_step(None, 0) == hotrg.EINVAL
     lib.hotrg_free(None)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors of hotrg_config / hotrg_obs against the C compiler's
+    # layout of the header (host gcc; no device)
+    import shutil
+    import subprocess
+    from paper_1906_06060_amd import hotrg
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "hotrg.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(hotrg_config), offsetof(hotrg_config, eig_max_sweeps),\n'
+        "         offsetof(hotrg_config, alloc), offsetof(hotrg_config, mem_budget), sizeof(hotrg_obs),\n"
+        "         offsetof(hotrg_obs, eig_residual));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [C.sizeof(hotrg.Config), hotrg.Config.eig_max_sweeps.offset, hotrg.Config.alloc.offset,
+            hotrg.Config.mem_budget.offset, C.sizeof(hotrg.Obs), hotrg.Obs.eig_residual.offset]
+    assert got == want
+
+
+@pytest.mark.parametrize("field,value", [("eig_max_sweeps", 1001), ("precision", 7)])
+def test_init_ex_rejects_bad_config_without_a_device(field, value):
+    from paper_1906_06060_amd import hotrg
+    lib = hotrg.load()
+    cfg = hotrg.Config()
+    cfg.impurities = 1
+    setattr(cfg, field, value)
+    out = C.c_void_p()
+    assert lib.hotrg_init_ex(0.1, 0.0, 4, C.byref(cfg), C.byref(out)) == hotrg.EINVAL
+    assert not out
+
+
+def test_init_ex_needs_alloc_and_free_together():
+    from paper_1906_06060_amd import hotrg
+    lib = hotrg.load()
+    cfg = hotrg.Config()
+    cfg.alloc = hotrg.ALLOC_FN(lambda n, ctx: None)
+    out = C.c_void_p()
+    assert lib.hotrg_init_ex(0.1, 0.0, 4, C.byref(cfg), C.byref(out)) == hotrg.EINVAL
+    assert b"together" in lib.hotrg_last_error()
+    assert not out
+
+
+def test_truncate_rejects_a_null_context():
+    from paper_1906_06060_amd import hotrg
+    lib = hotrg.load()
+    assert lib.hotrg_truncate(None, 0) == hotrg.EINVAL

@@ -133,3 +133,37 @@ def test_autograd_function_gives_energy_and_magnetisation(H):
     magnetisation = h.grad.item() / beta0
     assert energy == pytest.approx(-tb[2], rel=1e-9)
     assert magnetisation == pytest.approx(th[2] / beta0, rel=1e-8)
+
+
+@pytest.mark.parametrize("h", [0.0, 1e-4])
+@pytest.mark.parametrize("beta", [0.1480, 0.1497, 0.1510])
+def test_backward_dcut8_against_central_differences(H, beta, h):
+    # the forward-plus-adjoint configuration at Dcut = 8 (FP64; 8 steps, so
+    # steps 4-8 run at dims 8^4 with 64 x 64 eigenproblems): E = -dlnZ/dbeta
+    # and M = dlnZ/dh against central differences of the FP64 forward with
+    # delta = 1e-5 (truncation error ~ delta^2 f'''/6, rounding ~ 1e-16 / delta);
+    # at h = 0 the Z2 symmetry makes dlnZ/dh exactly zero
+    dcut, n, d = 8, 8, 1e-5
+    lnz, db, dh = gpu_grad(H, beta, h, dcut, n)
+
+    def f(b, hh):
+        with H.Context(b, hh, dcut, impurities=False) as ctx:
+            for k in range(n):
+                ctx.step(k % 4)
+            return ctx.lnz()
+    fd_b = (f(beta + d, h) - f(beta - d, h)) / (2 * d)
+    print(f"beta={beta} h={h}: dlnZ/dbeta {db:.12f} (FD {fd_b:.12f}), dlnZ/dh {dh:.3e}")
+    assert db == pytest.approx(fd_b, rel=1e-6)
+    if h == 0.0:
+        assert dh == 0.0
+    else:
+        fd_h = (f(beta, h + d) - f(beta, h - d)) / (2 * d)
+        assert dh == pytest.approx(fd_h, rel=1e-4)
+
+
+def test_backward_keeps_z2_exactly_at_zero_field_mixed_precision(H):
+    # bf16x3 forward and reverse GEMMs from step 4; at h = 0 every tensor of
+    # the chain has exact parity zeros, so dlnZ/dh vanishes exactly
+    lnz, db, dh = gpu_grad(H, 0.1497, 0.0, 6, 8, precision=H.BF16X3, mixed_from_step=4)
+    assert dh == 0.0
+    assert math.isfinite(db) and db > 0

@@ -1,0 +1,190 @@
+"""The C ABI's resource and failure contract on the GPU: device memory from the
+caller's allocator (torch's caching allocator through ctypes callbacks),
+HOTRG_ENOMEM from a NULL allocation or the memory budget followed by
+HOTRG_ESTATE, eigensolver non-convergence and undefined derivatives reported
+as HOTRG_ENUMERIC, checkpoint memory returned, and the environment/eigh stage
+on its own (hotrg_truncate).
+
+Every failure is forced from the host (an allocator that returns NULL, a
+budget, a sweep cap of one, a gap threshold no spectrum can pass): every
+kernel runs to its normal end.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_1906_06060_amd import hotrg
+    hotrg.load()
+    return hotrg
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def test_device_memory_comes_from_torch(H):
+    import torch
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    alloc = H.TorchAllocator(_stream())
+    with H.Context(0.15, 0.0, 6, allocator=alloc) as ctx:
+        for n in range(3):
+            ctx.step(n % 4)
+        ob = ctx.observables()
+        held = torch.cuda.memory_allocated() - before
+        print(f"context holds {ob['device_bytes']} bytes; torch's allocator grew by {held}")
+        assert ob["device_bytes"] > 0
+        assert alloc.bytes_held == ob["device_bytes"]
+        assert held >= ob["device_bytes"]
+    torch.cuda.synchronize()
+    assert alloc.bytes_held == 0
+    assert torch.cuda.memory_allocated() == before
+
+
+def test_default_context_uses_torch_allocator(H):
+    with H.Context(0.15, 0.0, 4) as ctx:
+        assert isinstance(ctx.allocator, H.TorchAllocator)
+        ctx.step(0)
+        assert ctx.allocator.bytes_held == ctx.observables()["device_bytes"]
+
+
+def test_null_allocation_at_init_is_enomem(H):
+    alloc = H.TorchAllocator(_stream(), fail_after=3)
+    with pytest.raises(H.HotrgError) as e:
+        H.Context(0.15, 0.0, 4, allocator=alloc)
+    assert e.value.code == H.ENOMEM
+    assert alloc.bytes_held == 0          # the partial context was unwound
+
+
+def test_null_allocation_in_a_step_is_enomem_then_estate(H):
+    # count the allocations of init, then let the first step's operand
+    # buffers fail
+    probe = H.TorchAllocator(_stream())
+    H.Context(0.15, 0.0, 4, allocator=probe).close()
+    alloc = H.TorchAllocator(_stream(), fail_after=probe.calls)
+    ctx = H.Context(0.15, 0.0, 4, allocator=alloc)
+    with pytest.raises(H.HotrgError) as e:
+        ctx.step(0)
+    assert e.value.code == H.ENOMEM
+    with pytest.raises(H.HotrgError) as e:
+        ctx.step(0)
+    assert e.value.code == H.ESTATE
+    with pytest.raises(H.HotrgError) as e:
+        ctx.lnz()
+    assert e.value.code == H.ESTATE
+    ctx.close()
+    assert alloc.bytes_held == 0
+
+
+def test_memory_budget(H):
+    with pytest.raises(H.HotrgError) as e:
+        H.Context(0.15, 0.0, 4, mem_budget=1 << 20)
+    assert e.value.code == H.ENOMEM
+    # enough for init, not for the first step's operands
+    probe = H.Context(0.15, 0.0, 4)
+    init_bytes = probe.observables()["device_bytes"]
+    probe.close()
+    ctx = H.Context(0.15, 0.0, 4, mem_budget=init_bytes)
+    with pytest.raises(H.HotrgError) as e:
+        ctx.step(0)
+    assert e.value.code == H.ENOMEM and "mem_budget" in str(e.value)
+    with pytest.raises(H.HotrgError) as e:
+        ctx.step(0)
+    assert e.value.code == H.ESTATE
+    ctx.close()
+
+
+def test_eigensolver_sweep_cap_is_enumeric(H):
+    # step 2 of a Dcut = 4 flow diagonalises 16 x 16 environments, which one
+    # Jacobi sweep cannot converge
+    with H.Context(0.15, 0.0, 4, eig_max_sweeps=1) as ctx:
+        ctx.step(0)          # environments of 4 x 4 at most: untruncated, no solve
+        with pytest.raises(H.HotrgError) as e:
+            ctx.step(1)
+        assert e.value.code == H.ENUMERIC and "converge" in str(e.value)
+        with pytest.raises(H.HotrgError) as e:
+            ctx.lnz()
+        assert e.value.code == H.ESTATE
+
+
+def test_eigensolver_sweeps_reported(H):
+    with H.Context(0.15, 0.0, 8) as ctx:
+        worst = 0
+        for n in range(5):
+            ctx.step(n % 4)
+            ob = ctx.observables()
+            worst = max(worst, ob["eig_sweeps"])
+            assert ob["eig_residual"] <= 1e-24 or ob["eig_sweeps"] < 40
+        print(f"most Jacobi sweeps in a 5-step Dcut = 8 flow: {worst}")
+        assert 0 < worst < 40
+
+
+def test_backward_refuses_a_cut_without_gap(H):
+    # a gap threshold no spectrum can pass flags every cut; the reverse pass
+    # refuses (the isometry derivative has 1 / (lam_i - lam_j) with no gap)
+    # before any device work and leaves the context usable
+    with H.Context(0.15, 0.01, 3, impurities=False, keep_checkpoints=True, tau_deg=2.0) as ctx:
+        for n in range(3):
+            ctx.step(n % 4)
+        assert ctx.observables()["flagged"] == 1
+        with pytest.raises(H.HotrgError) as e:
+            ctx.backward()
+        assert e.value.code == H.ENUMERIC and "gap" in str(e.value)
+        assert math.isfinite(ctx.lnz())
+
+
+def test_checkpoint_memory_is_returned(H):
+    D = 4
+    T = synth.z2_tensor((D, D, D, D), seed=3)
+    with H.Context(0.15, 0.0, D, impurities=False, keep_checkpoints=True) as ctx:
+        for n in range(4):
+            ctx.step(n % 4)
+        with_ckpts = ctx.observables()["device_bytes"]
+        ctx.set_state(T, n=4)
+        base = ctx.observables()["device_bytes"]
+        assert base < with_ckpts
+        for cycle in range(3):
+            ctx.set_state(T, n=4)
+            ctx.step(cycle % 4)
+            ctx.step((cycle + 1) % 4)
+            ctx.set_state(T, n=4)
+            assert ctx.observables()["device_bytes"] == base
+        with pytest.raises(H.HotrgError) as e:
+            ctx.backward()
+        assert e.value.code == H.ESTATE
+
+
+def test_truncate_equals_the_step_stage(H):
+    # hotrg_truncate then hotrg_step on the same state: same decisions and
+    # spectra, and the state and step count untouched by the truncate call
+    beta, dcut = 0.1497, 5
+    with H.Context(beta, 0.0, dcut) as ctx:
+        for n in range(3):
+            ctx.step(n % 4)
+        T0 = ctx.tensor(0)
+        dims0 = ctx.dims()
+        ctx.truncate(3)
+        assert ctx.dims() == dims0
+        assert np.array_equal(ctx.tensor(0), T0)
+        a = ctx.observables()
+        spec = {(q, s): ctx.spectrum(q, s) for q in range(3) for s in range(2)}
+        Us = {q: ctx.isometry(q) for q in range(3)}
+        ctx.step(3)
+        b = ctx.observables()
+        assert a["last_side"] == b["last_side"] and a["last_k"] == b["last_k"]
+        for (q, s), v in spec.items():
+            assert np.array_equal(v, ctx.spectrum(q, s))
+        for q, U in Us.items():
+            assert np.array_equal(U, ctx.isometry(q))

@@ -329,3 +329,80 @@ def test_bf16x3_flow_error_bound_against_fp64(H):
         assert abs(b["m_imp"] - a["m_imp"]) <= 1e-4
         print(f"n={a['n']} dlnz={abs(b['lnz_per_site'] - a['lnz_per_site']) / a['lnz_per_site']:.2e} "
               f"de={abs(b['e_imp'] - a['e_imp']):.2e} dm={abs(b['m_imp'] - a['m_imp']):.2e}")
+
+
+# ------------------------- environment / eigh stage at full size ----
+@pytest.mark.parametrize("D,axis", [(8, 3), (10, 3), (12, 1)])
+def test_truncate_full_size_matches_oracle(H, D, axis):
+    # identical seeded Z2 tensor of dims D^4 in both: the GPU's squeezed
+    # environments (12 Grams of D^2 x D^2, K = D^6) and Jacobi eigensolves of
+    # n = D^2 = 64 / 100 / 144 against the oracle's Gram-form environments and
+    # LAPACK eigh: spectra relative to lam_1 (1e-13), decisions exactly,
+    # projectors U U^T (1e-10)
+    T = synth.z2_tensor((D, D, D, D), seed=900 + D)
+    Us, _, decs = OH.isometries(T, axis, D, None)
+    with H.Context(0.15, 0.0, D, impurities=False) as ctx:
+        ctx.set_state(T, n=4)
+        ctx.truncate(axis)
+        ob = ctx.observables()
+        print(f"D={D}: Jacobi sweeps {ob['eig_sweeps']}, off-diagonal residual {ob['eig_residual']:.1e}, "
+              f"min cut gap {ob['min_cut_gap']:.2e}")
+        for dec in decs:
+            q = dec.nu
+            assert dec.truncated
+            for side in (0, 1):
+                sg = ctx.spectrum(q, side)
+                so = dec.spectra[side]
+                assert len(sg) == D * D
+                np.testing.assert_allclose(sg / so[0], so / so[0], rtol=0, atol=1e-13)
+            assert ob["last_side"][q] == dec.side
+            assert ob["last_k"][q] == dec.k
+            Ug = ctx.isometry(q)
+            U = Us[q]
+            assert Ug.shape == U.shape
+            np.testing.assert_allclose(Ug @ Ug.T, U @ U.T, rtol=0, atol=1e-10)
+        assert ob["flagged"] == 0
+
+
+def test_flow_dcut8_matches_stored_values(H):
+    # FP64 flow at beta = 0.1497, h = 1e-5, Dcut = 8 (steps 4-6 at dims 8^4,
+    # 64 x 64 environments) against tests/golden/dcut8_beta01497_h1e-5_6steps.json,
+    # written from the oracle by tests/golden/make_golden.py: c_n and lnZ/N to
+    # 1e-10 relative, impurity e, m and X to 1e-8, dims, kept k and chosen
+    # side exactly, the chosen environment spectra to 1e-13 lam_1
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "dcut8_beta01497_h1e-5_6steps.json")))
+    with H.Context(gold["beta"], gold["h"], gold["dcut"]) as ctx:
+        for w in gold["steps"]:
+            ctx.step(w["axis"])
+            g = ctx.observables()
+            assert list(g["dims"]) == w["dims"]
+            assert g["last_cn"] == pytest.approx(w["c_n"], rel=1e-10)
+            assert g["lnz_per_site"] == pytest.approx(w["lnz_per_site"], rel=1e-10)
+            assert g["e_imp"] == pytest.approx(w["e_imp"], abs=1e-8)
+            assert g["m_imp"] == pytest.approx(w["m_imp"], rel=1e-8, abs=1e-12)
+            assert g["X"] == pytest.approx(w["X"], abs=1e-8)
+            for d in w["truncated"]:
+                assert g["last_k"][d["axis"]] == d["k"]
+                assert g["last_side"][d["axis"]] == d["side"]
+                so = np.array(d["spectrum"])
+                sg = ctx.spectrum(d["axis"], d["side"])
+                np.testing.assert_allclose(sg / so[0], so / so[0], rtol=0, atol=1e-13)
+
+
+# ----------------- D = 10 sampled contraction, 64 x 64 entries ----
+@pytest.mark.parametrize("axis", [3, 0])
+def test_contraction_sampled_d10_bf16x3_64x64(H, axis):
+    # the bench's launch configuration (bf16x3, T | S_m | S_e stacked rows,
+    # K slices of 10^5 padded to 100032) on 64 sampled rows x 64 columns
+    w = _sampled_parity(H, 10, axis, H.BF16X3, True, 64, 6e-5, seed=51 + axis)
+    print(f"bf16x3 D=10 axis {axis}: worst scaled error over 64 x 64 x 3 entries {w:.3e}")
+
+
+def test_contraction_sampled_d10_fp64(H):
+    # the FP64 GEMM at D = 10 (pure T): K = 10^7 terms per entry summed in a
+    # different order from the oracle's; |error| <= 1e-13 |row| |col|
+    w = _sampled_parity(H, 10, 2, H.FP64, False, 32, 1e-13, seed=61)
+    print(f"fp64 D=10: worst scaled error {w:.3e}")
