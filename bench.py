@@ -26,7 +26,7 @@ PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
 # HBM bytes per GEMM call (main + tail dispatch + fix-up) of the bf16x3 GEMM at this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # plain 2 GiB copy); valid only while the kernel source is the one profiled.
-GEMM_TRAFFIC_BYTES = 311375665375
+GEMM_TRAFFIC_BYTES = {("dense", 10, True, True): 311375665375}
 GEMM_TRAFFIC_SRC_SHA = "bd6bbd792c297d0c"
 
 
@@ -52,8 +52,15 @@ def parse():
     p.add_argument("--h", type=float, default=0.0)
     p.add_argument("--precision", choices=["bf16x3", "fp64"], default="bf16x3")
     p.add_argument("--no-impurities", action="store_true")
+    p.add_argument("--dense", action="store_true",
+                   help="contract densely even at h = 0 (no Z2 block form), for comparison")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-rows", type=int, default=12)
+    p.add_argument("--cpu-dcut", type=int, default=8)
+    p.add_argument("--cpu-slices", type=int, default=2)
+    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 step sub-record")
+    p.add_argument("--fp64-pure", action="store_true",
+                   help="FP64 sub-record on a pure-T step (impurities off) instead of the bench workload")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint sub-record")
     p.add_argument("--adjoint", type=int, default=0, metavar="NSTEPS",
                    help="time an FP64 flow of NSTEPS steps with checkpoints plus hotrg_backward "
                         "(impurities off; Dcut from --dcut)")
@@ -95,38 +102,45 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}), flush=True)
 
 
-def cpu_baseline(dcut, rows):
-    """The CPU oracle on a bounded sample of the same step: `rows` x `rows`
-    entries of the new tensor of a D = dcut step, each from its definition
-    (oracle.sample), on seeded Z2 inputs of the same shape.  Reported as the
-    algorithmic flop rate 2 K per entry (K = D^7)."""
+def cpu_baseline(dcut, nslices):
+    """The CPU oracle's own contraction (oracle.hotrg.coarse_grain: NumPy with
+    BLAS-backed tensordot, its own contraction order) on a bounded part of a
+    steady-state step: `nslices` of the D^2 output (m1, m2) slices of one
+    Dcut = `dcut` step of T (seeded Z2 input of dims D^4, seeded isometries
+    D^2 x D), timed on the host.  Reported as the algorithmic rate
+    2 D^15 (nslices / D^2) / t, with the projected full pure-T step time."""
     import numpy as np
-    from oracle import sample as OS
+    from oracle import hotrg as OH
     from tests import synth
+    threads, blas = os.cpu_count(), "unknown"
     try:
         import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        threads = max(i.get("num_threads", 1) for i in info) if info else os.cpu_count()
+        info = [i for i in threadpoolctl.threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            threads = max(i.get("num_threads", 1) for i in info)
+            blas = ",".join(sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info}))
     except Exception:
-        threads = os.cpu_count()
+        pass
     D = dcut
     T = synth.z2_tensor((D, D, D, D), seed=5)
     Us = {q: synth.isometry(D * D, D, seed=50 + q) for q in range(3)}
-    rs = synth.sample_indices((D, D, D, D), rows, seed=60)
-    cs = synth.sample_indices((D, D, D, D), rows, seed=61)
+    pairs = [(i // D, i % D) for i in range(nslices)]
     t0 = time.perf_counter()
-    OS.step_entries(T, T, Us, 3, rs, cs)
+    out = OH.coarse_grain(T, T, Us, 3, slices=pairs)
     dt = time.perf_counter() - t0
-    K = D ** 7
-    flops = 2.0 * rows * rows * K
+    assert np.isfinite(out).all()
+    flops = 2.0 * D ** 15 * nslices / D ** 2
     return {
         "value": flops / dt / 1e12,
         "unit": "TFLOP/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{rows}x{rows} entries of one D={D} step (K={K}) from the definition, "
-                  f"seeded Z2 inputs; {dt:.1f} s; projected full pure step "
-                  f"{dt * (D ** 4) ** 2 / rows ** 2:.3g} s",
+        "blas": blas,
+        "host_cpus": os.cpu_count(),
+        "sample": f"oracle.hotrg.coarse_grain of one steady-state Dcut={D} step of T (dims {D}^4, "
+                  f"2 D^15 = {2.0 * D ** 15:.3g} flop), {nslices} of its {D * D} output (m1, m2) slices "
+                  f"in {dt:.1f} s on {threads} BLAS threads; projected full pure-T step "
+                  f"{dt * D * D / nslices:.1f} s",
     }
 
 
@@ -304,6 +318,63 @@ def table_run(a):
                                   "lnz_per_site": lnz, "dlnz_dbeta": db, "dlnz_dh": dh}), flush=True)
 
 
+def fp64_step(a, D, imp):
+    """The plain FP64 path on the same flow: the three ramp-up steps, then one
+    timed steady-state step (FP64 environments, eigh and contraction)."""
+    import torch
+    from paper_1906_06060_amd import hotrg as H
+    ctx = H.Context(a.beta, a.h, D, precision=H.FP64, impurities=imp, dense_only=a.dense)
+    for n in range(3):
+        ctx.step(n)
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ctx.gemm_stats()
+    ob = ctx.observables()
+    ctx.close()
+    dense = 2.0 * (3 if imp else 1) * D ** 15
+    gemm_s = st["ms"] / 1e3
+    print(f"[bench] fp64 step {dt:.2f} s", file=sys.stderr, flush=True)
+    return {
+        "step_s": round(dt, 3),
+        "rows": "T+S_m+S_e" if imp else "T",
+        "dense_flops": dense,
+        "tflops_dense": round(dense / dt / 1e12, 3),
+        "executed_flops": st["flops"],
+        "gemm_s": round(gemm_s, 3),
+        "gemm_tflops_executed": round(st["flops"] / gemm_s / 1e12, 3) if gemm_s > 0 else None,
+        "gemm_frac_of_fp64_peak": round(st["flops"] / gemm_s / PEAK_FP64, 4) if gemm_s > 0 else None,
+        "lnz_per_site": ob["lnz_per_site"],
+    }
+
+
+def adjoint_step(a, D, nsteps=4):
+    """Forward flow of `nsteps` pure-T steps with per-step checkpoints (three
+    ramp-up steps and one steady-state step, bf16x3 from step 4) and the
+    reverse pass hotrg_backward: E = -dlnZ/dbeta, M = dlnZ/dh."""
+    import torch
+    from paper_1906_06060_amd import hotrg as H
+    ctx = H.Context(a.beta, a.h, D, precision=H.BF16X3, impurities=False, keep_checkpoints=True,
+                    dense_only=a.dense)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(nsteps):
+        ctx.step(n % 4)
+    lnz = ctx.lnz()
+    t1 = time.perf_counter()
+    db, dh = ctx.backward()
+    t2 = time.perf_counter()
+    ob = ctx.observables()
+    ctx.close()
+    print(f"[bench] adjoint: forward {t1 - t0:.2f} s, reverse {t2 - t1:.2f} s", file=sys.stderr, flush=True)
+    return {"steps": nsteps, "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+            "device_gb": round(ob["device_bytes"] / 1e9, 2), "lnz_per_site": lnz,
+            "energy_per_site": -db, "dlnz_dh": dh}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -336,7 +407,7 @@ def main():
     prec = H.BF16X3 if a.precision == "bf16x3" else H.FP64
     imp = not a.no_impurities
     D = a.dcut
-    ctx = H.Context(a.beta, a.h, D, precision=prec, impurities=imp)
+    ctx = H.Context(a.beta, a.h, D, precision=prec, impurities=imp, dense_only=a.dense)
     axis = 0
     t_setup = time.perf_counter()
     for _ in range(3):                      # ramp-up steps (dims grow to Dcut)
@@ -362,13 +433,18 @@ def main():
     ctx.close()
 
     rows = (3 if imp else 1) * D ** 4
+    # the method's count of the step (dense O(D^15) contraction, Sec. 2 cost
+    # paragraph); the Z2 block form at h = 0 executes about a quarter of it
     step_flops = 2.0 * rows * D ** 4 * D ** 7
     sec = elapsed / a.steps
     tflops = step_flops / sec / 1e12
+    exec_flops = st["flops"] / a.steps      # GEMM flops the engine launched per step
+    block = bool(ob["block_sparse"])
     peak = PEAK_BF16 if prec == H.BF16X3 else PEAK_FP64
     issue = 3.0 if prec == H.BF16X3 else 1.0
     gemm_s = st["ms"] / 1e3
     achieved = st["flops"] / gemm_s if gemm_s > 0 else float("nan")
+    traffic_key = ("z2" if block else "dense", D, imp, prec == H.BF16X3)
     line = {
         "metric": "HOTRG step time & TFLOP/s (% MFMA peak) at Dcut=10, mixed vs FP64",
         "value": round(tflops, 3),
@@ -387,7 +463,13 @@ def main():
                         f"{'bf16x3' if prec == H.BF16X3 else 'fp64'} contraction, "
                         f"{'T+S_m+S_e rows' if imp else 'T rows'} (M={rows}, N={D ** 4}, K={D ** 7})",
             "beta": a.beta, "h": a.h, "dcut": D, "dims": list(dims),
-            "step_flops": step_flops, "pct_mfma_peak_issued": round(100 * issue * tflops * 1e12 / peak, 2),
+            "contraction": ("Z2 block form (h = 0: two parity-class GEMMs per K slice)" if block else "dense"),
+            "step_flops": step_flops,
+            "flop_count": "value = step_flops / step time, step_flops = 2 M N K of the dense contraction "
+                          "(the method's O(D^15) count); executed_flops_per_step = what the GEMMs ran",
+            "executed_flops_per_step": exec_flops,
+            "tflops_executed": round(exec_flops / sec / 1e12, 3),
+            "pct_mfma_peak_issued": round(100 * issue * exec_flops / sec / peak, 2),
             "setup_s": round(setup_s, 2),
             "lnz_per_site": ob["lnz_per_site"], "nn_imp": ob["nn_imp"], "m_imp": ob["m_imp"], "X": ob["X"],
         },
@@ -399,8 +481,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "issued_frac": round(issue * achieved / peak, 4),
-            "traffic": (GEMM_TRAFFIC_BYTES if (gemm_source_sha() == GEMM_TRAFFIC_SRC_SHA and D == 10 and imp
-                                                and prec == H.BF16X3) else None),
+            "traffic": (GEMM_TRAFFIC_BYTES.get(traffic_key) if gemm_source_sha() == GEMM_TRAFFIC_SRC_SHA
+                        else None),
             "traffic_unit": "bytes per GEMM call (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "launches": st["launches"],
             "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 3),
@@ -417,8 +499,12 @@ def main():
         "operand_products": round((ph["contraction_ms"] - ph["gemm_ms"]) / n_ph, 2),
         "normalise_permute": round(ph["normalise_ms"] / n_ph, 2),
     }
+    if prec == H.BF16X3 and not a.no_fp64:
+        line["fp64"] = fp64_step(a, D, imp and not a.fp64_pure)
+    if prec == H.BF16X3 and not a.no_adjoint:
+        line["adjoint"] = adjoint_step(a, D)
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(D, a.cpu_rows)
+        line["cpu_baseline"] = cpu_baseline(a.cpu_dcut, a.cpu_slices)
     print(json.dumps(line), flush=True)
 
 

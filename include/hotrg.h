@@ -78,14 +78,32 @@ typedef struct {
     void *alloc_ctx;
     size_t mem_budget;    /* most device bytes the context may hold at once; an allocation
                              that would exceed it fails with HOTRG_ENOMEM; 0 -> no limit */
+    int dense_only;       /* 1: always contract densely; 0: at h = 0 use the Z2 block form
+                             (below) whenever the state carries parity labels */
 } hotrg_config;
+
+/* Z2 block form of the contraction (h = 0).  At zero field Eq. (2.1) is
+ * invariant under sigma -> -sigma, so every bond index carries a parity and
+ * T, S_e are even, S_m odd: T^(0) from init has exact zeros on its odd
+ * entries, and every isometry column of the FP64 eigensolver lies in one
+ * parity sector (the Jacobi never rotates across an exactly zero block).  The
+ * library tracks these labels (from init at h = 0, from hotrg_set_state when
+ * the given tensors have exact zeros on the parity-violating entries with
+ * bond parity i mod 2, and from the isometry columns after every step; a
+ * column with non-zero rows of both parities drops the labels for the rest of
+ * the flow).  A step with labels, other than the first step's S_e . S_e
+ * pairing, contracts in blocks: per K slice the K indices of each parity class
+ * meet only operand rows and columns of one class, so the product splits into
+ * two GEMMs of about (M/2)(N/2)(K/2) -- a quarter of the dense work -- and
+ * the output's parity-violating half is never formed.  Results equal the
+ * dense contraction up to summation order. */
 
 /* Set up the one-site state of Eqs. (2.2) and (2.6) with bond dimension 2:
  *   W = [[sqrt cosh b, sqrt sinh b], [sqrt cosh b, -sqrt sinh b]] (W W^T = bond matrix, Eq. (2.1)),
  *   T^(0) = sum_s e^{b h s} prod_8 W[s, i],  S^(0) = same with an extra factor s,
- * normalised by c_0 = |T^(0)|_F.  beta >= 0 (ferromagnetic), h finite, 1 <= dcut <= 12
+ * normalised by c_0 = |T^(0)|_F.  beta >= 0 (ferromagnetic), h finite, 1 <= dcut <= 13
  * (HOTRG_EINVAL otherwise): the environment matrices are at most dcut^2 x dcut^2, and the
- * Gram, eigensolver and adjoint kernels use LDS tiles and buffers sized for 144 rows.
+ * eigensolver and adjoint kernels use LDS buffers sized for 169 rows.
  * hotrg_init uses the defaults (FP64, impurities on, no checkpoints). */
 int hotrg_init(double beta, double h, int dcut, hotrg_ctx **out);
 int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotrg_ctx **out);
@@ -124,6 +142,7 @@ typedef struct {
     size_t device_bytes;/* device memory held by the context */
     int eig_sweeps;     /* most Jacobi sweeps one eigendecomposition of the last step took */
     double eig_residual;/* largest squared off-diagonal / total norm those solves left */
+    int block_sparse;   /* 1 if the last step contracted in the Z2 block form (hotrg_config) */
 } hotrg_obs;
 
 /* Observables at the current step (impurity ratios need impurities = 1).
@@ -151,6 +170,7 @@ int hotrg_backward(hotrg_ctx *ctx, double *dlnz_dbeta, double *dlnz_dh);
 
 void hotrg_free(hotrg_ctx *ctx);
 const char *hotrg_last_error(void);
+
 
 /* ---- state access for parity tests and checkpoint/resume ------------------ */
 

@@ -338,10 +338,13 @@ def _step_slice(t1: np.ndarray, t2: np.ndarray, Us: dict, transverse: list, pivo
 PIVOT_ABOVE = 1 << 24      # elements of t1 . t2 above which the pivot order is used
 
 
-def coarse_grain(T1: np.ndarray, T2: np.ndarray, Us: dict, mu: int, pivot: bool | None = None) -> np.ndarray:
+def coarse_grain(T1: np.ndarray, T2: np.ndarray, Us: dict, mu: int, pivot: bool | None = None,
+                 slices=None) -> np.ndarray:
     """New (unnormalised) tensor of a step along mu, Eqs. (2.8)-(2.9) in d dims.
 
     Sliced over the two output mu-legs; see _step_slice for the two orders.
+    `slices` (a list of (m1, m2) pairs) computes only those output slices and
+    leaves the rest zero (used to time a bounded part of a large step).
     """
     d = T1.ndim // 2
     transverse = [nu for nu in range(d) if nu != mu]
@@ -360,11 +363,11 @@ def coarse_grain(T1: np.ndarray, T2: np.ndarray, Us: dict, mu: int, pivot: bool 
     if pivot is None:
         pivot = T1m[0].size * T2m[0].size // max(1, T1m.shape[-1]) > PIVOT_ABOVE
     idx = [slice(None)] * (2 * d)
-    for m1 in range(Dm1):
-        for m2 in range(Dm2):
-            sl = _step_slice(T1m[m1], T2m[m2], Us, transverse, pivot)
-            idx[2 * mu], idx[2 * mu + 1] = m1, m2
-            out[tuple(idx)] = sl
+    pairs = slices if slices is not None else [(m1, m2) for m1 in range(Dm1) for m2 in range(Dm2)]
+    for m1, m2 in pairs:
+        sl = _step_slice(T1m[m1], T2m[m2], Us, transverse, pivot)
+        idx[2 * mu], idx[2 * mu + 1] = m1, m2
+        out[tuple(idx)] = sl
     return out
 
 

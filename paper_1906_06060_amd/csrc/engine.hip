@@ -55,7 +55,7 @@ constexpr double kSideTie = 1e-11;
 // an eigensolve that reaches the sweep cap still counts as converged when the
 // squared off-diagonal norm it leaves is below this fraction of the total
 constexpr double kEigResidOk = 1e-24;
-constexpr int kMaxEnvN = 144;
+constexpr int kMaxEnvN = 169;  // environments of D^2 x D^2, D <= 13
 
 }  // namespace
 
@@ -78,17 +78,17 @@ struct hotrg_ctx {
     double *y1 = nullptr, *y2 = nullptr;             // cap each
     double *gram_part = nullptr;
     size_t gram_part_cap = 0;
-    double *G = nullptr;     // 2 * 144^2 (one pair of Grams at a time)
-    double *E = nullptr;     // 6 * 144^2
-    double *lam = nullptr;   // 6 * 144
-    double *V = nullptr;     // 6 * 144^2
+    double *G = nullptr;     // 2 * 169^2 (one pair of Grams at a time)
+    double *E = nullptr;     // 6 * 169^2
+    double *lam = nullptr;   // 6 * 169
+    double *V = nullptr;     // 6 * 169^2
     double *jwork = nullptr; // 2 * 2 * 145^2
     int *sweeps = nullptr;
     double *resid = nullptr;
-    double *U[3] = {nullptr, nullptr, nullptr};  // chosen isometries, 144^2 each, row-major n x k
+    double *U[3] = {nullptr, nullptr, nullptr};  // chosen isometries, 169^2 each, row-major n x k
     double *partials = nullptr;                   // 1024
     double *scal = nullptr;                       // 64
-    double *obs = nullptr;                        // 3 + 144
+    double *obs = nullptr;                        // 3 + 169
     DevBuf f64_slices;                            // FP64 operand slices
     DevBuf x3_slices;                             // bf16 hi/lo operand slices
     DevBuf gemm_tail;                             // second k-halves of the GEMM's last round of tiles
@@ -118,6 +118,25 @@ struct hotrg_ctx {
     bool ph_pending = false;
     double phase_ms[3] = {0, 0, 0};
     long long phase_steps = 0;
+
+    // Z2 parity of every bond index (h = 0): valid while z2 is set.  A step
+    // whose isometry columns each lie in one parity sector keeps it (the new
+    // labels are those sectors); the contraction of such a step runs in the
+    // block form (step_z2) unless dense_only is configured.
+    bool z2 = false;
+    std::vector<uint8_t> par[4];
+    std::vector<uint8_t> new_par[4];
+    bool step_z2 = false;
+    struct Z2Layout {
+        uint32_t N[2];      // rows (= columns) of one tensor per parity class
+        uint32_t Kc[2];     // inner K indices per parity class
+        uint64_t ldk[2];    // operand row length per class (bf16: padded to 64)
+        uint32_t R[2];      // stacked A rows of GEMM class g
+        uint64_t coff[2];   // offset of C_g in cbuf
+    } z2l{};
+    std::vector<uint32_t> rtab_h, ktab_h;  // host copies (kept alive for the uploads)
+    uint32_t *rtab = nullptr, *ktab = nullptr;
+    DevBuf z2_slices;
 
     // per-step checkpoints for the reverse pass (keep_checkpoints = 1)
     struct Checkpoint {
@@ -498,7 +517,7 @@ int isometries(hotrg_ctx *c, const double *T, const uint64_t lst[8], const int l
             c->Ucols[q] = nmat;
             continue;
         }
-        if (nmat > kMaxEnvN) return set_err(HOTRG_EINVAL, "environment larger than 144 x 144");
+        if (nmat > kMaxEnvN) return set_err(HOTRG_EINVAL, "environment larger than 169 x 169");
         double *Eb = c->E + (size_t)(2 * i) * kMaxEnvN * kMaxEnvN;
         for (int side = 0; side < 2; ++side) {
             int leg = 2 * i + side;
@@ -558,6 +577,112 @@ int isometries(hotrg_ctx *c, const double *T, const uint64_t lst[8], const int l
     return HOTRG_OK;
 }
 
+// Parity class tables of a Z2 block-form step (see ExpandParams): rows (and
+// columns) (a, b, mu1, c) of the GEMM with the new labels of the transverse
+// axes and the mu labels, inner K indices (b1', c1', a2, b2, c2) of a slice
+// with the old labels (b1' counted in the slice parity when a slice fixes
+// it).  Positions count each class in natural order.  Also fills the block
+// sizes: R_g = N_g (pure T) or N_g + N_{1-g} + N_g (T | S_m | S_e).
+int build_z2_tables(hotrg_ctx *c, int mu, const int tv[3], const int k[3], int Eb, int nA) {
+    const int *D = c->dims;
+    const int Da = D[tv[0]], Db = D[tv[1]], Dc = D[tv[2]], Dm = D[mu];
+    const int ka = k[0], kb = k[1], kc = k[2];
+    const auto &pa = c->new_par[tv[0]], &pb = c->new_par[tv[1]], &pc = c->new_par[tv[2]], &pm = c->par[mu];
+    const auto &oa = c->par[tv[0]], &ob = c->par[tv[1]], &oc = c->par[tv[2]];
+    if ((int)pa.size() != ka || (int)pb.size() != kb || (int)pc.size() != kc || (int)pm.size() != Dm ||
+        (int)oa.size() != Da || (int)ob.size() != Db || (int)oc.size() != Dc)
+        return set_err(HOTRG_EINVAL, "Z2 labels do not match the bond dimensions");
+    auto &zl = c->z2l;
+    const uint32_t M = (uint32_t)ka * kb * Dm * kc;
+    auto &rt = c->rtab_h;
+    rt.resize(M);
+    uint32_t cnt[2] = {0, 0}, r = 0;
+    for (int a = 0; a < ka; ++a)
+        for (int b = 0; b < kb; ++b)
+            for (int m = 0; m < Dm; ++m)
+                for (int cc = 0; cc < kc; ++cc) {
+                    const int p = pa[a] ^ pb[b] ^ pm[m] ^ pc[cc];
+                    rt[r++] = (p ? Z2_PAR : 0u) | cnt[p]++;
+                }
+    const uint32_t Ks = (uint32_t)Eb * Dc * Da * Db * Dc;
+    auto &kt = c->ktab_h;
+    kt.resize(Ks);
+    uint32_t kcnt[2] = {0, 0}, kk = 0;
+    for (int b1 = 0; b1 < Eb; ++b1)
+        for (int c1 = 0; c1 < Dc; ++c1)
+            for (int a2 = 0; a2 < Da; ++a2)
+                for (int b2 = 0; b2 < Db; ++b2)
+                    for (int c2 = 0; c2 < Dc; ++c2) {
+                        const int p = (Eb == Db ? ob[b1] : 0) ^ oc[c1] ^ oa[a2] ^ ob[b2] ^ oc[c2];
+                        kt[kk++] = (p ? Z2_PAR : 0u) | kcnt[p]++;
+                    }
+    for (int g = 0; g < 2; ++g) {
+        zl.N[g] = cnt[g];
+        zl.Kc[g] = kcnt[g];
+        zl.R[g] = nA == 1 ? cnt[g] : M + cnt[g];
+    }
+    zl.coff[0] = 0;
+    zl.coff[1] = (uint64_t)zl.R[0] * zl.N[0];
+    if (zl.coff[1] + (uint64_t)zl.R[1] * zl.N[1] > 3 * (uint64_t)c->cap)
+        return set_err(HOTRG_EINVAL, "Z2 output blocks exceed the output buffer");
+    const size_t Dmax = (size_t)std::max(c->dcut, 2);
+    if (!c->rtab) TRY(alloc_n(c, &c->rtab, Dmax * Dmax * Dmax * Dmax));
+    if (!c->ktab) TRY(alloc_n(c, &c->ktab, Dmax * Dmax * Dmax * Dmax * Dmax));
+    HIP_TRY(c, hipMemcpyAsync(c->rtab, rt.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->ktab, kt.data(), sizeof(uint32_t) * Ks, hipMemcpyHostToDevice, c->stream));
+    return HOTRG_OK;
+}
+
+// Turns the last isometry product described by x into the Z2 block scatter
+// (natural row length Ks, slice parity zs, tensor parity zP, first rows off[g]
+// of the tensor in class g) into the blocks out / hi / lo, with host checks
+// that every write stays inside its block.
+int z2_scatter(hotrg_ctx *c, XP &x, uint64_t Ks, uint32_t zs, uint32_t zP, const uint32_t off[2], uint64_t rows_cap,
+               bool mixed, double *const out[2], uint16_t *const hi[2], uint16_t *const lo[2]) {
+    ExpandParams &p = x.p;
+    const auto &zl = c->z2l;
+    if (p.nsum != p.L2 || p.L2 > 13 || (size_t)p.L1 * p.L2 * p.L2 * sizeof(double) > 48 * 1024)
+        return set_err(HOTRG_EINVAL, "Z2 scatter: unsupported product shape");
+    // rows of class g written: off[g] + (rows of parity zP ^ g); columns < Kc[b] <= ldk[b]
+    for (int g = 0; g < 2; ++g)
+        if ((uint64_t)off[g] + zl.N[zP ^ (uint32_t)g] > rows_cap)
+            return set_err(HOTRG_EINVAL, "Z2 scatter rows out of bounds");
+    if (Ks != (uint64_t)zl.Kc[0] + zl.Kc[1] || zl.ldk[0] < zl.Kc[0] || zl.ldk[1] < zl.Kc[1])
+        return set_err(HOTRG_EINVAL, "Z2 scatter columns out of bounds");
+    p.z2 = 1;
+    // run form: every thread dim steps either whole rows (stride a multiple
+    // of Ks) or K digits, the first loop steps whole rows, and the second
+    // loop plus the K digits stay below Ks (no carry into the row part)
+    {
+        bool run = p.o1 % Ks == 0 && p.o1 / Ks < (1u << 20) && p.o2 < Ks;
+        uint64_t kmax = (uint64_t)(p.L2 - 1) * p.o2;
+        for (int d = 0; d < p.nd && run; ++d) {
+            const uint64_t st = p.out_st[d], ext = p.ext[d].d;
+            if (st % Ks == 0) continue;
+            if (st >= Ks) run = false;
+            kmax += (ext - 1) * st;
+        }
+        if (run && kmax < Ks) {
+            p.z2 = 2;
+            p.zrs = (uint32_t)(p.o1 / Ks);
+        }
+    }
+    p.zld = make_fastdiv((uint32_t)Ks);
+    p.rtab = c->rtab;
+    p.ktab = c->ktab;
+    p.zs = zs;
+    p.zP = zP;
+    for (int b = 0; b < 2; ++b) {
+        p.zrow_off[b] = off[b];
+        p.zld_out[b] = (uint32_t)zl.ldk[b];
+        p.zpkb[b] = (uint32_t)(zl.ldk[b] / PACK_K);
+        p.zout[b] = mixed ? nullptr : out[b];
+        p.zhi[b] = mixed ? hi[b] : nullptr;
+        p.zlo[b] = mixed ? lo[b] : nullptr;
+    }
+    return HOTRG_OK;
+}
+
 // Contraction of one step with isometries c->U[0..2] (n_i x k_i, row-major).
 int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     const int *D = c->dims;
@@ -606,7 +731,55 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     double *Asl = nullptr, *Bsl = nullptr;
     uint16_t *Ah = nullptr, *Al = nullptr, *Bh = nullptr, *Bl = nullptr;
     double *tail = nullptr;
-    if (mixed) {
+    // Z2 block form: per parity class of the inner K index one operand block
+    // pair (A rows of the GEMM class, B rows = columns of that class)
+    const bool z2 = c->step_z2 && nB == 1;
+    auto &zl = c->z2l;
+    double *zA[2] = {nullptr, nullptr}, *zB[2] = {nullptr, nullptr};
+    uint16_t *zAh[2] = {nullptr, nullptr}, *zAl[2] = {nullptr, nullptr};
+    uint16_t *zBh[2] = {nullptr, nullptr}, *zBl[2] = {nullptr, nullptr};
+    uint64_t z2_arows = 0, z2_brows = 0;  // rows allocated per A / B block
+    if (z2) {
+        TRY(build_z2_tables(c, mu, tv, k, Eb, nA));
+        const uint32_t Nmax = std::max(zl.N[0], zl.N[1]);
+        const uint64_t Amax = (uint64_t)std::max(zl.R[0], zl.R[1]);
+        z2_arows = Amax;
+        z2_brows = Nmax;
+        uint64_t need = 0, offs[2][2];
+        for (int b = 0; b < 2; ++b) {
+            zl.ldk[b] = mixed ? ((uint64_t)zl.Kc[b] + 63) / 64 * 64 : zl.Kc[b];
+            const uint64_t ar = mixed ? packed_rows(Amax) : Amax, br = mixed ? packed_rows(Nmax) : Nmax;
+            offs[b][0] = need;
+            need += ar * zl.ldk[b];
+            offs[b][1] = need;
+            need += br * zl.ldk[b];
+        }
+        // (block offsets are 64-bit; the GEMMs take rows and k as int)
+        if (Amax * zl.ldk[0] >= (1ull << 31) || Amax * zl.ldk[1] >= (1ull << 31))
+            return set_err(HOTRG_ENOMEM, "Z2 operand block exceeds 2^31 elements");
+        if (mixed) {
+            TRY(ensure(c, c->z2_slices, sizeof(uint16_t) * 2 * need));
+            TRY(ensure(c, c->gemm_tail, sizeof(double) * GEMM_TAIL_MAX_TILES * 256 * 256));
+            tail = (double *)c->gemm_tail.p;
+            uint16_t *base = (uint16_t *)c->z2_slices.p;
+            for (int b = 0; b < 2; ++b) {
+                zAh[b] = base + offs[b][0];
+                zAl[b] = base + need + offs[b][0];
+                zBh[b] = base + offs[b][1];
+                zBl[b] = base + need + offs[b][1];
+            }
+            // padding columns (Kc .. ldk) are never written and must be zero
+            if (zl.ldk[0] != zl.Kc[0] || zl.ldk[1] != zl.Kc[1])
+                HIP_TRY(c, hipMemsetAsync(base, 0, sizeof(uint16_t) * 2 * need, c->stream));
+        } else {
+            TRY(ensure(c, c->z2_slices, sizeof(double) * need));
+            double *base = (double *)c->z2_slices.p;
+            for (int b = 0; b < 2; ++b) {
+                zA[b] = base + offs[b][0];
+                zB[b] = base + offs[b][1];
+            }
+        }
+    } else if (mixed) {
         TRY(ensure(c, c->x3_slices, sizeof(uint16_t) * 2 * pslice * (nA + nB)));
         TRY(ensure(c, c->gemm_tail, sizeof(double) * GEMM_TAIL_MAX_TILES * 256 * 256));
         tail = (double *)c->gemm_tail.p;
@@ -649,7 +822,10 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     // K-part strides of an operand row (b1', c1', a2, b2, c2) and row strides
     const uint64_t ks0 = (uint64_t)Dc * Da * Db * Dc, ks1 = (uint64_t)Da * Db * Dc, ks2 = (uint64_t)Db * Dc,
                    ks3 = Dc;
-    const uint64_t rs0 = (uint64_t)kb * Dm * kc * ld, rs1 = (uint64_t)Dm * kc * ld, rs2 = (uint64_t)kc * ld;
+    // (the Z2 scatter splits natural offsets r Ks + k, so its row length is Ks)
+    const uint64_t ldn = z2 ? Ks : ld;
+    const uint64_t rs0 = (uint64_t)kb * Dm * kc * ldn, rs1 = (uint64_t)Dm * kc * ldn, rs2 = (uint64_t)kc * ldn;
+    bool z2_init[2] = {false, false};
 
     bool first_slice = true;
     const int nslices = Dm * Da * (Db / Eb);
@@ -657,6 +833,9 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     for (int g = 0; g < Dm; ++g) {       // alpha
       for (int f = 0; f < Da; ++f) {     // a1'
         for (int e0 = 0; e0 < Db; e0 += Eb) {  // first b1' of the slice
+            // parity of the indices the slice fixes (alpha, a1', and b1' when Eb = 1)
+            const uint32_t zs = z2 ? (uint32_t)(c->par[mu][g] ^ c->par[tv[0]][f] ^ (Eb == 1 ? c->par[tv[1]][e0] : 0))
+                                   : 0u;
             // ---- A rows: T1 in {T, S_m, S_e}
             for (int t = 0; t < nA; ++t) {
                 const uint64_t off = f * lst[1] + g * lst[7] + e0 * lst[3];
@@ -695,10 +874,17 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.tdim(Dc, y2s[4], ks1);
                     x.tdim(Da, y2s[5], ks2);
                     x.tdim(Db, y2s[6], ks3);
-                    x.loops(kc, 1, ld, Dc, kc, 1);
+                    x.loops(kc, 1, ldn, Dc, kc, 1);
                     x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
-                    if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
-                    if (mixed && stack) {  // rows t*M .. t*M + M - 1 of one packed block
+                    if (!x.fits(c->cap, usz[2], M * ldn)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
+                    if (z2) {
+                        // A rows of tensor t in GEMM class g start at: T 0, S_m N_g, S_e M
+                        uint32_t off[2];
+                        for (int gg = 0; gg < 2; ++gg)
+                            off[gg] = t == 0 ? 0u : (t == 1 ? zl.N[gg] : (uint32_t)M);
+                        TRY(z2_scatter(c, x, Ks, zs, t == 1 ? 1u : 0u, off, z2_arows, mixed, zA, zAh, zAl));
+                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, nullptr, nullptr, c->stream);
+                    } else if (mixed && stack) {  // rows t*M .. t*M + M - 1 of one packed block
                         x.packed(ld, (uint32_t)(t * M));
                         launch_iso_expand(x.done(), c->y2, Uc, nullptr, Ah, Al, c->stream);
                     } else if (mixed) {
@@ -750,10 +936,14 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     x.tdim(Da, z2s[4], ks2);
                     x.tdim(Db, z2s[5], ks3);
                     x.tdim(Dc, z2s[6], 1);
-                    x.loops(kc, 1, ld, Dc, (uint64_t)Dc * kc, ks1);
+                    x.loops(kc, 1, ldn, Dc, (uint64_t)Dc * kc, ks1);
                     x.sum(Dc, z2s[7], kc);
-                    if (!x.fits(c->cap, usz[2], slice)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
-                    if (mixed) {
+                    if (!x.fits(c->cap, usz[2], M * ldn)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
+                    if (z2) {
+                        const uint32_t off[2] = {0u, 0u};
+                        TRY(z2_scatter(c, x, Ks, zs, 0u, off, z2_brows, mixed, zB, zBh, zBl));
+                        launch_iso_expand(x.done(), c->y2, Uc, nullptr, nullptr, nullptr, c->stream);
+                    } else if (mixed) {
                         x.packed(ld);
                         launch_iso_expand(x.done(), c->y2, Uc, nullptr, Bh + pslice * bidx, Bl + pslice * bidx,
                                           c->stream);
@@ -762,7 +952,34 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                 }
             }
             // ---- GEMMs: C rows (+)= A B^T
-            for (int bidx = 0; bidx < nB; ++bidx) {
+            if (z2) {
+                // block b (inner K parity b) feeds GEMM class g = b ^ zs:
+                // C_g[R_g x N_g] (+)= A_b B_b^T over the Kc[b] indices of the
+                // block; in mixed precision both products go in one launch
+                X3Gemm xg[2];
+                int nx = 0;
+                double fl = 0;
+                hipEvent_t e0 = next_event(c), e1 = next_event(c);
+                if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
+                for (int b = 0; b < 2; ++b) {
+                    const int gcls = b ^ (int)zs;
+                    const uint32_t R = zl.R[gcls], N = zl.N[gcls], Kb = zl.Kc[b];
+                    if (R == 0 || N == 0 || Kb == 0) continue;
+                    double *Cg = c->cbuf + zl.coff[gcls];
+                    const int acc = z2_init[gcls] ? 1 : 0;
+                    z2_init[gcls] = true;
+                    if (mixed)
+                        xg[nx++] = X3Gemm{zAh[b], zAl[b], zBh[b], zBl[b], Cg, (int)R, 1, (int)N, (int)zl.ldk[b], N, acc};
+                    else
+                        launch_gemm_f64(zA[b], zB[b], Cg, (int)R, (int)N, (int)Kb, Kb, Kb, N, acc, c->stream);
+                    fl += 2.0 * (double)R * (double)N * (double)Kb;
+                }
+                if (mixed && nx > 0) launch_gemm_bf16x3_multi(xg, nx, c->stream, tail);
+                if (e1) HIP_TRY(c, hipEventRecord(e1, c->stream));
+                c->gemm_launches++;
+                c->gemm_flops += fl;
+            }
+            for (int bidx = 0; bidx < (z2 ? 0 : nB); ++bidx) {
                 const int row0 = bidx == 0 ? 0 : 2;
                 const int rows = bidx == 0 ? nA_shared : 1;
                 hipEvent_t e0 = next_event(c), e1 = next_event(c);
@@ -787,6 +1004,9 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
         }
       }
     }
+    if (z2)
+        for (int gcls = 0; gcls < 2; ++gcls)
+            if (!z2_init[gcls]) launch_zero(c->cbuf + zl.coff[gcls], (size_t)zl.R[gcls] * zl.N[gcls], c->stream);
     return HOTRG_OK;
 }
 
@@ -797,10 +1017,21 @@ int finish_step(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     for (int i = 0; i < 3; ++i) Dn[tv[i]] = k[i];
     const int Dm = c->dims[mu];
     const uint64_t M = (uint64_t)k[0] * k[1] * k[2] * Dm;
-    launch_sumsq(c->cbuf, (size_t)(M * M), c->partials, 1024, c->scal, c->stream);
+    const auto &zl = c->z2l;
     double ss = 0;
-    HIP_TRY(c, hipMemcpyAsync(&ss, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->step_z2) {
+        // the T rows of both classes: the first N_g rows of C_g (row length N_g)
+        double s2[2] = {0, 0};
+        for (int g = 0; g < 2; ++g)
+            launch_sumsq(c->cbuf + zl.coff[g], (size_t)zl.N[g] * zl.N[g], c->partials, 1024, c->scal + g, c->stream);
+        HIP_TRY(c, hipMemcpyAsync(s2, c->scal, sizeof(s2), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        ss = s2[0] + s2[1];
+    } else {
+        launch_sumsq(c->cbuf, (size_t)(M * M), c->partials, 1024, c->scal, c->stream);
+        HIP_TRY(c, hipMemcpyAsync(&ss, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     // accumulate GEMM event times of this step
     for (size_t e = 0; e + 1 < c->ev_used; e += 2) {
         float ms = 0;
@@ -831,8 +1062,36 @@ int finish_step(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     if (mx >= M * M || pp.total != M * M || M * M > c->cap)
         return set_err(HOTRG_EINVAL, "normalise / permute launch out of bounds");
     const int nt = c->cfg.impurities ? 3 : 1;
-    for (int t = 0; t < nt; ++t)
-        launch_permute(pp, c->cbuf + (size_t)t * M * M, c->state[t], 1.0 / cn, c->stream);
+    if (c->step_z2) {
+        // gather from the block form: row part of a canonical index from the
+        // backward legs, column part from the forward legs
+        Z2UnpackParams up{};
+        up.nd = 8;
+        up.total = (uint32_t)(M * M);
+        for (int l = 0; l < 8; ++l) {
+            up.ext[l] = make_fastdiv((uint32_t)ext[l]);
+            const uint32_t sq = (l % 2 == 0) ? st[l] / (uint32_t)rowst : st[l];
+            up.rst[l] = (l % 2 == 0) ? sq : 0u;
+            up.cst[l] = (l % 2 == 0) ? 0u : sq;
+        }
+        up.rtab = c->rtab;
+        for (int g = 0; g < 2; ++g) {
+            up.C[g] = c->cbuf + zl.coff[g];
+            up.N[g] = zl.N[g];
+        }
+        for (int t = 0; t < nt; ++t) {
+            up.P = t == 1 ? 1u : 0u;
+            for (int g = 0; g < 2; ++g) {
+                up.row_off[g] = t == 0 ? 0u : (t == 1 ? zl.N[g] : (uint32_t)M);
+                if ((uint64_t)up.row_off[g] + zl.N[up.P ^ (uint32_t)g] > zl.R[g])
+                    return set_err(HOTRG_EINVAL, "Z2 unpack rows out of bounds");
+            }
+            launch_z2_unpack(up, c->state[t], 1.0 / cn, c->stream);
+        }
+    } else {
+        for (int t = 0; t < nt; ++t)
+            launch_permute(pp, c->cbuf + (size_t)t * M * M, c->state[t], 1.0 / cn, c->stream);
+    }
     TRY(check_launch(c, "normalise / permute"));
     c->n += 1;
     c->last_cn = cn;
@@ -931,6 +1190,40 @@ int flush_phases(hotrg_ctx *c) {
     return HOTRG_OK;
 }
 
+// Parity of every isometry column (Z2 state only): the parity of the merged
+// rows (i1, i2) it is non-zero on, p(i1) ^ p(i2).  *pure = false as soon as
+// one column has non-zero rows of both parities (or none).
+int z2_new_labels(hotrg_ctx *c, const int tv[3], const int k[3], const double *const *Uhost, bool *pure) {
+    *pure = true;
+    std::vector<double> U;
+    for (int i = 0; i < 3; ++i) {
+        const int q = tv[i], D = c->dims[q], n = D * D;
+        const double *u;
+        if (Uhost) {
+            u = Uhost[q];
+        } else {
+            U.resize((size_t)n * k[i]);
+            HIP_TRY(c, hipMemcpyAsync(U.data(), c->U[i], sizeof(double) * n * k[i], hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            u = U.data();
+        }
+        const auto &p = c->par[q];
+        auto &np = c->new_par[q];
+        np.assign(k[i], 0);
+        for (int j = 0; j < k[i]; ++j) {
+            int seen = 0;  // bit 0: an even row is non-zero, bit 1: an odd row
+            for (int r = 0; r < n; ++r)
+                if (u[(size_t)r * k[i] + j] != 0.0) seen |= 1 << (p[r / D] ^ p[r % D]);
+            if (seen != 1 && seen != 2) {
+                *pure = false;
+                return HOTRG_OK;
+            }
+            np[j] = (uint8_t)(seen >> 1);
+        }
+    }
+    return HOTRG_OK;
+}
+
 int run_step_body(hotrg_ctx *c, int axis, const int tv[3], const int k[3]) {
     HIP_TRY(c, hipEventRecord(c->ph[1], c->stream));
     TRY(contract(c, axis, tv, k));
@@ -995,12 +1288,29 @@ int do_step(hotrg_ctx *c, int axis, const double *const *Uhost, const int *khost
     } else {
         TRY(isometries(c, c->state[0], lst, ldim, tv, axis, k));
     }
+    // Z2 labels of the new bonds; the block form needs them and a step that
+    // is not the S_e . S_e pairing of the first step (Eq. (2.8))
+    bool pure = false;
+    if (c->z2) {
+        int rz = z2_new_labels(c, tv, k, Uhost, &pure);
+        if (rz != HOTRG_OK) {
+            c->failed = true;
+            return rz;
+        }
+    }
+    c->step_z2 = pure && !c->cfg.dense_only && !(c->cfg.impurities && c->n == 0);
     int rc = c->cfg.keep_checkpoints ? save_checkpoint(c, axis, tv, k, Uhost != nullptr) : HOTRG_OK;
     if (rc != HOTRG_OK) {
         c->failed = true;
         return rc;
     }
     rc = run_step_body(c, axis, tv, k);
+    if (rc == HOTRG_OK && c->z2) {
+        if (pure)
+            for (int i = 0; i < 3; ++i) c->par[tv[i]] = c->new_par[tv[i]];
+        else
+            c->z2 = false;
+    }
     if (rc != HOTRG_OK) {
         // a failed step leaves the context failed; its checkpoint copy goes
         if (c->cfg.keep_checkpoints) {
@@ -1636,6 +1946,29 @@ int backward(hotrg_ctx *c, double *dbeta, double *dh) {
 
 }  // namespace
 
+// Observables from the traces of Eq. (2.5) and the A matrix of Eq. (3.2)
+// (Da x Da): ln Z / N, the impurity ratios of Eqs. (2.10), (2.12), and X of
+// Eq. (3.3).
+void obs_from_traces(double tr, double trm, double tre, const double *A, int Da, int n, double lnz_acc, double h,
+                     bool imp, hotrg_obs *o) {
+    // a state set by the caller may have Tr <= 0; ln Z is then undefined (NaN)
+    o->lnz_per_site = (tr > 0 && std::isfinite(tr)) ? lnz_acc + std::ldexp(std::log(tr), -n) : NAN;
+    o->trace = tr;
+    if (imp) {
+        o->m_imp = trm / tr;
+        o->nn_imp = tre / tr;
+        o->e_imp = -4.0 * o->nn_imp - h * o->m_imp;
+    } else {
+        o->m_imp = o->nn_imp = o->e_imp = NAN;
+    }
+    double trA = 0, trA2 = 0;
+    for (int t = 0; t < Da; ++t) {
+        trA += A[(size_t)t * Da + t];
+        for (int u = 0; u < Da; ++u) trA2 += A[(size_t)t * Da + u] * A[(size_t)u * Da + t];
+    }
+    o->X = trA * trA / trA2;
+}
+
 // =============================================================== C ABI ====
 extern "C" {
 
@@ -1646,7 +1979,7 @@ int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotr
     *out = nullptr;
     if (!(beta >= 0) || !std::isfinite(beta)) return set_err(HOTRG_EINVAL, "beta must be finite and >= 0");
     if (!std::isfinite(h)) return set_err(HOTRG_EINVAL, "h must be finite");
-    if (dcut < 1 || dcut > 12) return set_err(HOTRG_EINVAL, "dcut must be in 1..12");
+    if (dcut < 1 || dcut > 13) return set_err(HOTRG_EINVAL, "dcut must be in 1..13");
     hotrg_ctx *c = new hotrg_ctx();
     c->beta = beta;
     c->h = h;
@@ -1723,6 +2056,9 @@ int hotrg_init_ex(double beta, double h, int dcut, const hotrg_config *cfg, hotr
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(set_err(HOTRG_EDEVICE, "init kernels failed"));
     c->lnz_acc = std::log(c0);
     c->c0 = c0;
+    // at h = 0 the bond index 0 (column (1, 1) of W) is Z2-even, index 1 odd
+    c->z2 = (h == 0.0);
+    for (int q = 0; q < 4; ++q) c->par[q] = {0, 1};
     *out = c;
     return HOTRG_OK;
 }
@@ -1773,23 +2109,8 @@ int hotrg_observables(hotrg_ctx *c, hotrg_obs *o) {
     std::memset(o, 0, sizeof(*o));
     o->n = c->n;
     for (int q = 0; q < 4; ++q) o->dims[q] = c->dims[q];
-    // a state set by the caller may have Tr <= 0; ln Z is then undefined (NaN)
-    o->lnz_per_site = (tr > 0 && std::isfinite(tr)) ? c->lnz_acc + std::ldexp(std::log(tr), -c->n) : NAN;
-    o->trace = tr;
-    if (c->cfg.impurities) {
-        o->m_imp = trm / tr;
-        o->nn_imp = tre / tr;
-        o->e_imp = -4.0 * o->nn_imp - c->h * o->m_imp;
-    } else {
-        o->m_imp = o->nn_imp = o->e_imp = NAN;
-    }
-    int Da = c->dims[c->last_axis < 0 ? 3 : c->last_axis];
-    double trA = 0, trA2 = 0;
-    for (int t = 0; t < Da; ++t) {
-        trA += A[(size_t)t * Da + t];
-        for (int u = 0; u < Da; ++u) trA2 += A[(size_t)t * Da + u] * A[(size_t)u * Da + t];
-    }
-    o->X = trA * trA / trA2;
+    obs_from_traces(tr, trm, tre, A.data(), c->dims[c->last_axis < 0 ? 3 : c->last_axis], c->n, c->lnz_acc, c->h,
+                    c->cfg.impurities != 0, o);
     o->last_axis = c->last_axis;
     o->min_cut_gap = c->min_gap;
     o->flagged = c->flagged;
@@ -1802,6 +2123,7 @@ int hotrg_observables(hotrg_ctx *c, hotrg_obs *o) {
     o->device_bytes = c->device_bytes;
     o->eig_sweeps = c->eig_sweeps;
     o->eig_residual = c->eig_resid;
+    o->block_sparse = c->n > 0 && c->step_z2 ? 1 : 0;
     return HOTRG_OK;
 }
 
@@ -1865,6 +2187,44 @@ int hotrg_set_state(hotrg_ctx *c, const int dims[4], const double *T, const doub
     c->first_axis = n > 0 ? 0 : -1;
     c->last_axis = -1;
     c->ckpt_broken = true;
+    c->step_z2 = false;
+    // Z2 labels for a state given by the caller: at h = 0, bond parity
+    // i mod 2 if T and S_e vanish on every odd-parity entry and S_m on every
+    // even one (exactly); otherwise the state carries no labels
+    c->z2 = false;
+    if (c->h == 0.0) {
+        bool ok = true;
+        const double *ts[3] = {T, c->cfg.impurities ? Sm : nullptr, c->cfg.impurities ? Se : nullptr};
+        int ext[8];
+        for (int l = 0; l < 8; ++l) ext[l] = dims[l / 2];
+        for (int t = 0; t < 3 && ok; ++t) {
+            if (!ts[t]) continue;
+            const int want = t == 1 ? 1 : 0;
+            int idx[8] = {0, 0, 0, 0, 0, 0, 0, 0}, par = 0;
+            for (size_t e = 0; e < need; ++e) {
+                if (ts[t][e] != 0.0 && par != want) {
+                    ok = false;
+                    break;
+                }
+                // next multi-index (last leg fastest), parity updated incrementally
+                for (int l = 7; l >= 0; --l) {
+                    par ^= idx[l] & 1;
+                    if (++idx[l] < ext[l]) {
+                        par ^= idx[l] & 1;
+                        break;
+                    }
+                    idx[l] = 0;
+                }
+            }
+        }
+        if (ok) {
+            c->z2 = true;
+            for (int q = 0; q < 4; ++q) {
+                c->par[q].resize(dims[q]);
+                for (int i = 0; i < dims[q]; ++i) c->par[q][i] = (uint8_t)(i & 1);
+            }
+        }
+    }
     return HOTRG_OK;
 }
 

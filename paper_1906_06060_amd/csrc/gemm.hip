@@ -164,26 +164,48 @@ static_assert(KC % BK == 0, "a chunk is whole stages");
 // A holds `ntA` tensors of M rows, each padded to Mp = roundup(M, 256); a row
 // tile never straddles two tensors and its rows map to C rows t M + r (r < M).
 //
-// One launch covers the tiles t0 .. t0 + units - 1 of the tile order.  With
-// halves = 2 every tile is two units: k in [0, kmid) added into C as usual,
-// and k in [kmid, K) written to the 256 x 256 block `part` + (unit / 2) 2^16,
-// which gemm_tail_fixup_kernel adds into C afterwards (used for the last,
-// partly filled round of tiles, so that it takes half as long).
-__global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restrict__ Ah,
-                                                         const uint16_t *__restrict__ Al,
-                                                         const uint16_t *__restrict__ Bh,
-                                                         const uint16_t *__restrict__ Bl, double *__restrict__ C,
-                                                         int M, int Mp, int N, int K, size_t ldc, int accumulate,
-                                                         int tiles_m, int tiles_n, int t0, int halves, int kmid,
-                                                         double *__restrict__ part) {
+// One launch covers the tiles t0 .. t0 + units - 1 of the tile order of up
+// to two independent products (tiles below tiles0 belong to the first; a
+// launch over both fills the chip with the tiles of both).  With halves = 2
+// every tile is two units: k in [0, kmid) added into C as usual, and k in
+// [kmid, K) written to the 256 x 256 block `part` + (unit / 2) 2^16, which
+// gemm_tail_fixup_kernel adds into C afterwards (used for the last, partly
+// filled round of tiles, so that it takes half as long).
+struct Prob {
+    const uint16_t *Ah, *Al, *Bh, *Bl;
+    double *C;
+    int M, Mp, N, K;
+    size_t ldc;
+    int accumulate, tiles_m, tiles_n;
+};
+struct Launch {
+    Prob p[2];
+    int tiles0, t0, halves;
+    double *part;
+};
+
+__global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const Launch L) {
     extern __shared__ __align__(16) uint16_t smem[];
     char *lds = (char *)smem;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 2, wc = wave & 3;  // wave tile: rows wr*128.., cols wc*64..
     const int u = unit_of(blockIdx.x, gridDim.x);
+    const int halves = L.halves;
     const int hf = halves == 2 ? (u & 1) : 0;
+    const int tg = L.t0 + (halves == 2 ? (u >> 1) : u);
+    const int pi = tg >= L.tiles0 ? 1 : 0;
+    const Prob &P = L.p[pi];
+    const uint16_t *__restrict__ Ah = P.Ah;
+    const uint16_t *__restrict__ Al = P.Al;
+    const uint16_t *__restrict__ Bh = P.Bh;
+    const uint16_t *__restrict__ Bl = P.Bl;
+    double *__restrict__ C = P.C;
+    double *__restrict__ part = L.part;
+    const int M = P.M, Mp = P.Mp, N = P.N, K = P.K, accumulate = P.accumulate;
+    const size_t ldc = P.ldc;
+    const int kmid = K / 2 / BK * BK;
     int tm, tn;
-    tile_rc(t0 + (halves == 2 ? (u >> 1) : u), tiles_m, tiles_n, tm, tn);
+    tile_rc(tg - (pi ? L.tiles0 : 0), P.tiles_m, P.tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     const int tens = m0 / Mp, lrow0 = m0 - tens * Mp;  // tensor of this row tile, its first local row
     const int kbeg = hf ? kmid : 0, kend = (halves == 2 && !hf) ? kmid : K;
@@ -338,26 +360,46 @@ __global__ void __launch_bounds__(NT) gemm_bf16x3_kernel(const uint16_t *__restr
     if (first) flush();
 }
 
-// C tile of split tile s (tile t0 + s) += its second-half partial block.
-__global__ void __launch_bounds__(256) gemm_tail_fixup_kernel(const double *__restrict__ part, double *__restrict__ C,
-                                                              int M, int Mp, int N, size_t ldc, int tiles_m,
-                                                              int tiles_n, int t0) {
+// C tile of split tile s (tile t0 + s of the launch's tile order) += its
+// second-half partial block.
+__global__ void __launch_bounds__(256) gemm_tail_fixup_kernel(const Launch L) {
     const int s = blockIdx.x;
+    const int tg = L.t0 + s;
+    const int pi = tg >= L.tiles0 ? 1 : 0;
+    const Prob &P = L.p[pi];
     int tm, tn;
-    tile_rc(t0 + s, tiles_m, tiles_n, tm, tn);
+    tile_rc(tg - (pi ? L.tiles0 : 0), P.tiles_m, P.tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
-    const int tens = m0 / Mp, lrow0 = m0 - tens * Mp;
-    const double *p = part + (size_t)s * (BM * BN);
+    const int tens = m0 / P.Mp, lrow0 = m0 - tens * P.Mp;
+    const double *p = L.part + (size_t)s * (BM * BN);
     for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
         const int lr = e / BN, lc = e % BN;
-        if (lrow0 + lr < M && n0 + lc < N) C[(size_t)(tens * M + lrow0 + lr) * ldc + n0 + lc] += p[e];
+        if (lrow0 + lr < P.M && n0 + lc < P.N) P.C[(size_t)(tens * P.M + lrow0 + lr) * P.ldc + n0 + lc] += p[e];
     }
 }
 }  // namespace x3
 
-void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl, double *C,
-                        int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s, double *part) {
-    if (M <= 0 || N <= 0 || ntA <= 0) return;
+namespace {
+x3::Prob make_prob(const X3Gemm &g) {
+    x3::Prob p{};
+    p.Ah = g.Ah;
+    p.Al = g.Al;
+    p.Bh = g.Bh;
+    p.Bl = g.Bl;
+    p.C = g.C;
+    p.M = g.M;
+    p.Mp = (g.M + x3::BM - 1) / x3::BM * x3::BM;
+    p.N = g.N;
+    p.K = g.K;
+    p.ldc = g.ldc;
+    p.accumulate = g.accumulate;
+    p.tiles_m = g.ntA * (p.Mp / x3::BM);
+    p.tiles_n = (g.N + x3::BN - 1) / x3::BN;
+    return p;
+}
+}  // namespace
+
+void launch_gemm_bf16x3_multi(const X3Gemm *g, int count, hipStream_t s, double *part) {
     static bool attr_set = false;
     static int ncu = 0;
     if (!attr_set) {
@@ -369,25 +411,43 @@ void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *
             ncu = 0;
         attr_set = true;
     }
-    const int Mp = (M + x3::BM - 1) / x3::BM * x3::BM;
-    const int tm = ntA * (Mp / x3::BM), tn = (N + x3::BN - 1) / x3::BN;
-    const int tiles = tm * tn;
+    x3::Launch L{};
+    int n = 0;
+    for (int i = 0; i < count && n < 2; ++i)
+        if (g[i].M > 0 && g[i].N > 0 && g[i].ntA > 0 && g[i].K > 0) L.p[n++] = make_prob(g[i]);
+    if (n == 0) return;
+    if (n == 1) L.p[1] = L.p[0];
+    L.tiles0 = L.p[0].tiles_m * L.p[0].tiles_n;
+    const int tiles = L.tiles0 + (n == 2 ? L.p[1].tiles_m * L.p[1].tiles_n : 0);
+    if (n == 1) L.tiles0 = tiles;
     // One workgroup per CU at a time: the last round of tiles is partly
     // filled.  When it holds at most half the CUs (and there is a full round
-    // before it), its tiles run as two k-halves each, after the full rounds.
+    // before it), its tiles run as two k-halves each, after the full rounds
+    // (every K is a multiple of 64, so both halves are non-empty).
     const int rem = ncu > 0 ? tiles % ncu : 0;
-    const int kmid = K / 2 / x3::BK * x3::BK;
-    if (part && rem > 0 && rem <= ncu / 2 && rem <= GEMM_TAIL_MAX_TILES && tiles > ncu && kmid > 0) {
+    if (part && rem > 0 && rem <= ncu / 2 && rem <= GEMM_TAIL_MAX_TILES && tiles > ncu) {
         const int main = tiles - rem;
-        x3::gemm_bf16x3_kernel<<<main, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, Mp, N, K, ldc, accumulate,
-                                                                   tm, tn, 0, 1, K, nullptr);
-        x3::gemm_bf16x3_kernel<<<2 * rem, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, Mp, N, K, ldc,
-                                                                      accumulate, tm, tn, main, 2, kmid, part);
-        x3::gemm_tail_fixup_kernel<<<rem, 256, 0, s>>>(part, C, M, Mp, N, ldc, tm, tn, main);
+        L.part = nullptr;
+        L.t0 = 0;
+        L.halves = 1;
+        x3::gemm_bf16x3_kernel<<<main, x3::NT, x3::LDS_BYTES, s>>>(L);
+        L.part = part;
+        L.t0 = main;
+        L.halves = 2;
+        x3::gemm_bf16x3_kernel<<<2 * rem, x3::NT, x3::LDS_BYTES, s>>>(L);
+        x3::gemm_tail_fixup_kernel<<<rem, 256, 0, s>>>(L);
         return;
     }
-    x3::gemm_bf16x3_kernel<<<tiles, x3::NT, x3::LDS_BYTES, s>>>(Ah, Al, Bh, Bl, C, M, Mp, N, K, ldc, accumulate, tm,
-                                                                tn, 0, 1, K, nullptr);
+    L.part = nullptr;
+    L.t0 = 0;
+    L.halves = 1;
+    x3::gemm_bf16x3_kernel<<<tiles, x3::NT, x3::LDS_BYTES, s>>>(L);
+}
+
+void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl, double *C,
+                        int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s, double *part) {
+    const X3Gemm g{Ah, Al, Bh, Bl, C, M, ntA, N, K, ldc, accumulate};
+    launch_gemm_bf16x3_multi(&g, 1, s, part);
 }
 
 }  // namespace hotrg

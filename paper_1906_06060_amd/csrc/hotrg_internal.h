@@ -58,7 +58,32 @@ struct ExpandParams {
     FastDiv pld;
     uint32_t pkb;
     uint32_t prow0;  // packed layout: row of the operand block where this launch's row 0 goes
+    // Z2 block scatter (z2 = 1): the natural offset o = r zld + k of a
+    // row-major operand slice is split into a row r and a K index k; the
+    // tables give their parities (bit 31) and positions inside their parity
+    // class.  An output with inner K parity i goes to block i, GEMM class
+    // g = i ^ zs; it is structurally zero (not written) unless the row's
+    // parity is zP ^ g.  Block i gets row zrow_off[g] + position, column the
+    // K position; FP64 blocks are row-major with row length zld_out[i], bf16
+    // blocks packed with zpkb[i] = zld_out[i] / 32 k blocks per row tile.
+    int z2;
+    // z2 == 2: the run form (see iso_expand_z2run_kernel): the first loop
+    // steps whole rows (o1 = zrs * zld), the second stays inside the row
+    // (o2 < zld and no carry out of the K part), so a thread needs one row
+    // and N K lookups
+    uint32_t zrs;
+    FastDiv zld;
+    const uint32_t *rtab, *ktab;
+    uint32_t zs, zP;
+    uint32_t zrow_off[2];
+    uint32_t zld_out[2], zpkb[2];
+    double *zout[2];
+    uint16_t *zhi[2], *zlo[2];
 };
+
+// Z2 parity class tables: bit 31 = parity, low 31 bits = position of the
+// index within its class (natural order).
+constexpr uint32_t Z2_PAR = 0x80000000u;
 
 // Generic contraction of two strided views (reverse pass):
 //   out[z(o)] (+)= alpha * sum_s X[x(o) + x(s)] * Y[y(o) + y(s)]
@@ -114,7 +139,7 @@ void launch_sumsq(const double *x, size_t n, double *partials, int npartials, do
 void launch_trace_obs(const double *T0, const double *T1, const double *T2, const int D[4],
                       int axis, double *out, hipStream_t s);
 // G[(p, q), (p', q')] = sum_r X[p q r] X[p' q' r] for X given as R x K row-major
-// (R <= 144): split-K partials then a fixed-order reduction.
+// (R <= 288): split-K partials then a fixed-order reduction.
 void launch_gram(const double *X, int R, size_t K, double *partials, int nchunks, double *G,
                  hipStream_t s);
 // E[(p, q), (p', q')] = sum_{a, a'} G1[p a p' a'] G2[q a q' a']
@@ -127,6 +152,26 @@ void launch_zero(double *x, size_t n, hipStream_t s);
 // columns written as zero).  R * ld < 2^32.
 void launch_split_pack(const double *X, uint32_t R, uint32_t K, uint32_t ld, uint16_t *hi, uint16_t *lo,
                        hipStream_t s);
+
+// Z2 block form of the step's output -> canonical tensors.  C_g (g = 0, 1)
+// holds, for GEMM class g, rows [T rows of parity g | S_m rows of parity 1-g |
+// S_e rows of parity g] (positions from rtab) by the columns of parity g, row
+// length N_g.  Output element o of tensor t (canonical order of the new dims)
+// has row index sum_l digit_l rst[l] and column index sum_l digit_l cst[l];
+// entries whose row and column parities differ from the tensor's parity
+// (even T, S_e; odd S_m) are exact zeros.  out = scale * C value.
+struct Z2UnpackParams {
+    int nd;
+    uint32_t total;
+    FastDiv ext[PERM_MAXD];
+    uint32_t rst[PERM_MAXD], cst[PERM_MAXD];
+    const uint32_t *rtab;
+    const double *C[2];
+    uint32_t N[2];
+    uint32_t row_off[2];  // this tensor's first row in C_g
+    uint32_t P;           // tensor parity
+};
+void launch_z2_unpack(const Z2UnpackParams &p, double *out, double scale, hipStream_t s);
 
 // reverse pass (kernels_adjoint.hip)
 // LastProdParams contraction; partial: (n_o1 * n_o2 + 64) * L * N * N doubles
@@ -142,7 +187,7 @@ void launch_diag_set(double *T, const int D[4], const uint32_t diag_st[4], doubl
 void launch_site_dot(const double *Tbar, double wc, double ws, double dwc, double dws, double beta, double h,
                      double vu, double vd, double inv_c0, double *out, hipStream_t s);
 
-// Jacobi eigensolver: `count` symmetric n x n matrices (n <= 144) at A + i*n*n,
+// Jacobi eigensolver: `count` symmetric n x n matrices (n <= 169) at A + i*n*n,
 // eigenvalues (descending) to lam + i*n, eigenvectors as columns of V + i*n*n
 // (row-major, V[r*n + j] = component r of vector j).  work: 2*count*n*n doubles.
 // At most max_sweeps sweeps; sweeps[i] gets the number taken and resid[i] the
@@ -172,6 +217,17 @@ inline size_t packed_rows(size_t R) { return (R + PACK_ROWS - 1) / PACK_ROWS * P
 // `part` (may be null): scratch for the second k-halves of the last, partly
 // filled round of tiles, GEMM_TAIL_MAX_TILES blocks of 256 x 256 doubles.
 constexpr int GEMM_TAIL_MAX_TILES = 128;
+// Several independent bf16x3 products (at most two) in one launch: their
+// tiles form one list, so the chip is filled by the tiles of both and only
+// the last round of the combined list is partly filled.
+struct X3Gemm {
+    const uint16_t *Ah, *Al, *Bh, *Bl;
+    double *C;
+    int M, ntA, N, K;
+    size_t ldc;
+    int accumulate;
+};
+void launch_gemm_bf16x3_multi(const X3Gemm *g, int count, hipStream_t s, double *part);
 void launch_gemm_bf16x3(const uint16_t *Ah, const uint16_t *Al, const uint16_t *Bh, const uint16_t *Bl,
                         double *C, int M, int ntA, int N, int K, size_t ldc, int accumulate, hipStream_t s,
                         double *part);

@@ -328,8 +328,8 @@ __global__ void __launch_bounds__(kT) eigh_adjoint_kernel(const double *__restri
                                                           const double *__restrict__ lam,
                                                           const double *__restrict__ Ubar, int n, int k,
                                                           double *__restrict__ Ebar) {
-    __shared__ double Ksh[144 * 12];
-    __shared__ double Zsh[144 * 12];
+    __shared__ double Ksh[169 * 13];  // (n - k) x k, n <= 169, k <= 13
+    __shared__ double Zsh[169 * 13];  // n x k
     const int m = n - k;
     for (int idx = threadIdx.x; idx < m * k; idx += blockDim.x) {
         int j = idx / k, i = idx % k;
@@ -405,9 +405,12 @@ __global__ void __launch_bounds__(256) site_dot_kernel(const double *__restrict_
         odd ^= b;
     }
     const double sg = odd ? -1.0 : 1.0;
-    // T = vu m + vd sg m
-    const double dT_dbeta = h * vu * m + vu * dm - h * vd * sg * m + vd * sg * dm;
-    const double dT_dh = beta * vu * m - beta * vd * sg * m;
+    // T = vu m + vd sg m.  Written with the spin weights factored out: at
+    // h = 0 (vu = vd = 1) dT/dh is then exactly 0 on the even entries (a
+    // difference of two separately rounded products, which the compiler may
+    // fuse into one FMA, would leave the rounding error of one of them)
+    const double dT_dbeta = vu * (dm + h * m) + sg * vd * (dm - h * m);
+    const double dT_dh = beta * m * (vu - sg * vd);
     sb[i] = Tbar[i] * dT_dbeta;
     sh[i] = Tbar[i] * dT_dh;
     __syncthreads();

@@ -1,4 +1,4 @@
-// FP64 symmetric eigensolver for the environment matrices (n <= 144):
+// FP64 symmetric eigensolver for the environment matrices (n <= 169):
 // two-sided cyclic Jacobi with the round-robin ("circle") ordering, so every
 // round rotates n/2 disjoint (p, q) planes at once (Golub & Van Loan,
 // Matrix Computations, Sec. 8.5: the 2x2 symmetric Schur step and parallel
@@ -13,7 +13,7 @@
 namespace hotrg {
 
 constexpr int JT = 512;          // threads per matrix
-constexpr int J_MAXN = 144;
+constexpr int J_MAXN = 170;  // n <= 169, padded to even
 
 __device__ __forceinline__ int rr_player(int pos, int round, int m) {
     // position 0 is fixed, positions 1..m-1 rotate by `round`

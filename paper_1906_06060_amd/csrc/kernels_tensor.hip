@@ -254,6 +254,138 @@ __global__ void __launch_bounds__(kThreads) iso_expand_lds_kernel(ExpandParams p
     }
 }
 
+// Z2 block scatter of the last isometry product (see ExpandParams): the
+// destination of every output is looked up first, outputs that the parity
+// structure makes exactly zero are neither computed nor written, and the rest
+// go to their parity block (FP64 row-major, or bf16 hi / lo in the packed
+// layout).  Same arithmetic, in the same order, as iso_expand_lds_kernel.
+template <bool SPLIT, int N>
+__global__ void __launch_bounds__(kThreads) iso_expand_z2_kernel(ExpandParams p, const double *__restrict__ in,
+                                                                 const double *__restrict__ U) {
+    extern __shared__ double sZ[];  // [L1][N][N]
+    const int nU = p.L1 * N * N;
+    for (int idx = threadIdx.x; idx < nU; idx += blockDim.x) {
+        const int i = idx % N, l2 = (idx / N) % N, l1 = idx / (N * N);
+        sZ[idx] = U[l1 * p.u1 + l2 * p.u2 + i * p.us];
+    }
+    __syncthreads();
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < p.threads; t += gridDim.x * blockDim.x) {
+        uint32_t rem = t, ib = 0, ob = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.ext[k]);
+            uint32_t c = rem - q * p.ext[k].d;
+            ib += c * p.in_st[k];
+            ob += c * p.out_st[k];
+            rem = q;
+        }
+        double v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = in[ib + i * p.xs];
+        for (int l1 = 0; l1 < p.L1; ++l1) {
+            const double *ul = sZ + l1 * N * N;
+            const uint32_t o = ob + l1 * p.o1;
+#pragma unroll 1
+            for (int l2 = 0; l2 < N; ++l2) {
+                const uint32_t oo = o + l2 * p.o2;
+                const uint32_t r = fast_div(oo, p.zld);
+                const uint32_t k = oo - r * p.zld.d;
+                const uint32_t rt = p.rtab[r], kt = p.ktab[k];
+                const uint32_t blk = kt >> 31, g = blk ^ p.zs;
+                if ((rt >> 31) != (p.zP ^ g)) continue;  // structurally zero
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc = fma(ul[l2 * N + i], v[i], acc);
+                const uint32_t row = p.zrow_off[g] + (rt & ~Z2_PAR), col = kt & ~Z2_PAR;
+                if (SPLIT) {
+                    const uint16_t h = bf16_bits((float)acc);
+                    const size_t po = ((size_t)(row / PACK_ROWS) * p.zpkb[blk] + col / PACK_K) * (PACK_ROWS * PACK_K) +
+                                      (row % PACK_ROWS) * PACK_K + col % PACK_K;
+                    p.zhi[blk][po] = h;
+                    p.zlo[blk][po] = bf16_bits((float)(acc - bf16_value(h)));
+                } else {
+                    p.zout[blk][(size_t)row * p.zld_out[blk] + col] = acc;
+                }
+            }
+        }
+    }
+}
+
+// Run form of the Z2 scatter (z2 == 2): a thread splits its base offset
+// into (row, K) once, loads the class entries of its N outputs along the
+// second loop once, and per step of the first loop looks up one row: the row
+// decides the only block that can receive outputs (block = row parity ^ zP ^
+// zs), and the outputs whose K class is that block are computed and stored.
+template <bool SPLIT, int N>
+__global__ void __launch_bounds__(kThreads) iso_expand_z2run_kernel(ExpandParams p, const double *__restrict__ in,
+                                                                    const double *__restrict__ U) {
+    extern __shared__ double sZ[];  // [L1][N][N]
+    const int nU = p.L1 * N * N;
+    for (int idx = threadIdx.x; idx < nU; idx += blockDim.x) {
+        const int i = idx % N, l2 = (idx / N) % N, l1 = idx / (N * N);
+        sZ[idx] = U[l1 * p.u1 + l2 * p.u2 + i * p.us];
+    }
+    __syncthreads();
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < p.threads; t += gridDim.x * blockDim.x) {
+        uint32_t rem = t, ib = 0, ob = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.ext[k]);
+            uint32_t c = rem - q * p.ext[k].d;
+            ib += c * p.in_st[k];
+            ob += c * p.out_st[k];
+            rem = q;
+        }
+        const uint32_t r0 = fast_div(ob, p.zld);
+        const uint32_t k0 = ob - r0 * p.zld.d;
+        uint32_t kt[N];
+#pragma unroll
+        for (int l2 = 0; l2 < N; ++l2) kt[l2] = p.ktab[k0 + l2 * p.o2];
+        double v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = in[ib + i * p.xs];
+        for (int l1 = 0; l1 < p.L1; ++l1) {
+            const uint32_t rt = p.rtab[r0 + l1 * p.zrs];
+            const uint32_t blk = (rt >> 31) ^ p.zP ^ p.zs, g = blk ^ p.zs;
+            const uint32_t row = p.zrow_off[g] + (rt & ~Z2_PAR);
+            const double *ul = sZ + l1 * N * N;
+            const size_t rbase = SPLIT ? (size_t)(row / PACK_ROWS) * p.zpkb[blk] * (PACK_ROWS * PACK_K) +
+                                             (row % PACK_ROWS) * PACK_K
+                                       : (size_t)row * p.zld_out[blk];
+            uint16_t *hi = SPLIT ? p.zhi[blk] : nullptr;
+            uint16_t *lo = SPLIT ? p.zlo[blk] : nullptr;
+            double *out = SPLIT ? nullptr : p.zout[blk];
+#pragma unroll
+            for (int l2 = 0; l2 < N; ++l2) {
+                if ((kt[l2] >> 31) != blk) continue;  // structurally zero
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc = fma(ul[l2 * N + i], v[i], acc);
+                const uint32_t col = kt[l2] & ~Z2_PAR;
+                if (SPLIT) {
+                    const uint16_t h = bf16_bits((float)acc);
+                    const size_t po = rbase + (size_t)(col / PACK_K) * (PACK_ROWS * PACK_K) + col % PACK_K;
+                    hi[po] = h;
+                    lo[po] = bf16_bits((float)(acc - bf16_value(h)));
+                } else {
+                    out[rbase + col] = acc;
+                }
+            }
+        }
+    }
+}
+
+template <int N>
+void launch_iso_expand_z2(const ExpandParams &p, bool split, const double *in, const double *U, hipStream_t s) {
+    const size_t lds = (size_t)p.L1 * N * N * sizeof(double);
+    const int g = grid_for(p.threads, kThreads, 4096);
+    if (p.z2 == 2) {
+        if (split) iso_expand_z2run_kernel<true, N><<<g, kThreads, lds, s>>>(p, in, U);
+        else iso_expand_z2run_kernel<false, N><<<g, kThreads, lds, s>>>(p, in, U);
+        return;
+    }
+    if (split) iso_expand_z2_kernel<true, N><<<g, kThreads, lds, s>>>(p, in, U);
+    else iso_expand_z2_kernel<false, N><<<g, kThreads, lds, s>>>(p, in, U);
+}
+
 template <int N>
 void launch_iso_expand_lds(const ExpandParams &p, const double *in, const double *U, double *out, uint16_t *hi,
                            uint16_t *lo, hipStream_t s) {
@@ -387,6 +519,26 @@ void launch_iso_expand_pairs(const ExpandParams &p, bool run, const double *in, 
 void launch_iso_expand(const ExpandParams &pin, const double *in, const double *U, double *out, uint16_t *hi,
                        uint16_t *lo, hipStream_t s) {
     if (pin.threads == 0) return;
+    if (pin.z2) {
+        // the host checks nsum == L2 <= 13 and the LDS size (z2_expand_ok)
+        const bool split = pin.zhi[0] != nullptr;
+        switch (pin.L2) {
+            case 1: return launch_iso_expand_z2<1>(pin, split, in, U, s);
+            case 2: return launch_iso_expand_z2<2>(pin, split, in, U, s);
+            case 3: return launch_iso_expand_z2<3>(pin, split, in, U, s);
+            case 4: return launch_iso_expand_z2<4>(pin, split, in, U, s);
+            case 5: return launch_iso_expand_z2<5>(pin, split, in, U, s);
+            case 6: return launch_iso_expand_z2<6>(pin, split, in, U, s);
+            case 7: return launch_iso_expand_z2<7>(pin, split, in, U, s);
+            case 8: return launch_iso_expand_z2<8>(pin, split, in, U, s);
+            case 9: return launch_iso_expand_z2<9>(pin, split, in, U, s);
+            case 10: return launch_iso_expand_z2<10>(pin, split, in, U, s);
+            case 11: return launch_iso_expand_z2<11>(pin, split, in, U, s);
+            case 12: return launch_iso_expand_z2<12>(pin, split, in, U, s);
+            case 13: return launch_iso_expand_z2<13>(pin, split, in, U, s);
+            default: return;
+        }
+    }
     // The two output loops enter the product symmetrically; when the first
     // one has unit output stride, exchange them so that the run kernels
     // (unit stride on the second loop) apply.
@@ -421,6 +573,7 @@ void launch_iso_expand(const ExpandParams &pin, const double *in, const double *
             case 10: return launch_iso_expand_lds<10>(p, in, U, out, hi, lo, s);
             case 11: return launch_iso_expand_lds<11>(p, in, U, out, hi, lo, s);
             case 12: return launch_iso_expand_lds<12>(p, in, U, out, hi, lo, s);
+            case 13: return launch_iso_expand_lds<13>(p, in, U, out, hi, lo, s);
             default: break;
         }
     }
@@ -433,6 +586,34 @@ void launch_iso_expand(const ExpandParams &pin, const double *in, const double *
         if (run) iso_expand_kernel<false, true><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
         else iso_expand_kernel<false, false><<<g, kThreads, 0, s>>>(p, in, U, out, hi, lo);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Z2 block form -> canonical tensor (see Z2UnpackParams).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) z2_unpack_kernel(Z2UnpackParams p, double *__restrict__ out,
+                                                             double scale) {
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < p.total; o += gridDim.x * blockDim.x) {
+        uint32_t rem = o, r = 0, c = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            const uint32_t q = fast_div(rem, p.ext[k]);
+            const uint32_t d = rem - q * p.ext[k].d;
+            r += d * p.rst[k];
+            c += d * p.cst[k];
+            rem = q;
+        }
+        const uint32_t rt = p.rtab[r], ct = p.rtab[c];
+        const uint32_t g = ct >> 31;
+        double v = 0.0;
+        if (((rt >> 31) ^ g) == p.P)
+            v = scale * p.C[g][(size_t)(p.row_off[g] + (rt & ~Z2_PAR)) * p.N[g] + (ct & ~Z2_PAR)];
+        out[o] = v;
+    }
+}
+
+void launch_z2_unpack(const Z2UnpackParams &p, double *out, double scale, hipStream_t s) {
+    if (p.total == 0) return;
+    z2_unpack_kernel<<<grid_for(p.total), kThreads, 0, s>>>(p, out, scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,16 +731,24 @@ void launch_trace_obs(const double *T0, const double *T1, const double *T2, cons
 }
 
 // ---------------------------------------------------------------------------
-// Gram of the rows of X (R x K, row-major): split-K partial products by a
-// 16 x 16 thread grid, each thread owning up to 9 x 9 outputs (R <= 144).
+// Gram of the rows of X (R x K, row-major): split-K partial products.  The
+// R x R output is covered by tiles of GR_TILE x GR_TILE (blockIdx.y), each
+// computed by a 16 x 16 thread grid owning up to 9 x 9 outputs; the two row
+// ranges of a tile are staged in LDS per 16-k step.  Every output is one FMA
+// chain over its chunk's k in increasing order, whatever the tiling.
 // ---------------------------------------------------------------------------
 constexpr int GR_MAXB = 9;
+constexpr int GR_TILE = 16 * GR_MAXB;  // 144
 constexpr int GR_KB = 16;
+constexpr int GR_MAXR = 2 * GR_TILE;   // R <= 288 (environments up to 169 rows)
 
 __global__ void __launch_bounds__(256) gram_partial_kernel(const double *__restrict__ X, int R, size_t K,
-                                                          size_t chunk, double *__restrict__ partials) {
-    __shared__ double Xs[144][GR_KB + 1];
+                                                          size_t chunk, int ntile, double *__restrict__ partials) {
+    __shared__ double Xa[GR_TILE][GR_KB + 1];
+    __shared__ double Xb[GR_TILE][GR_KB + 1];
     const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
+    const int r0 = (blockIdx.y / ntile) * GR_TILE, c0 = (blockIdx.y % ntile) * GR_TILE;
+    const int Ra = min(GR_TILE, R - r0), Rb = min(GR_TILE, R - c0);
     size_t k0 = (size_t)blockIdx.x * chunk;
     size_t k1 = k0 + chunk < K ? k0 + chunk : K;
     double acc[GR_MAXB][GR_MAXB];
@@ -568,10 +757,11 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(const double *__restr
 #pragma unroll
         for (int b = 0; b < GR_MAXB; ++b) acc[a][b] = 0.0;
     for (size_t kb = k0; kb < k1; kb += GR_KB) {
-        for (int idx = threadIdx.x; idx < R * GR_KB; idx += 256) {
+        for (int idx = threadIdx.x; idx < GR_TILE * GR_KB; idx += 256) {
             int r = idx / GR_KB, kk = idx % GR_KB;
             size_t k = kb + kk;
-            Xs[r][kk] = k < k1 ? X[(size_t)r * K + k] : 0.0;
+            Xa[r][kk] = (k < k1 && r < Ra) ? X[(size_t)(r0 + r) * K + k] : 0.0;
+            Xb[r][kk] = (k < k1 && r < Rb) ? X[(size_t)(c0 + r) * K + k] : 0.0;
         }
         __syncthreads();
 #pragma unroll 4
@@ -579,10 +769,8 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(const double *__restr
             double xa[GR_MAXB], xb[GR_MAXB];
 #pragma unroll
             for (int a = 0; a < GR_MAXB; ++a) {
-                int r = ti + 16 * a;
-                xa[a] = r < R ? Xs[r][kk] : 0.0;
-                int c = tj + 16 * a;
-                xb[a] = c < R ? Xs[c][kk] : 0.0;
+                xa[a] = Xa[ti + 16 * a][kk];
+                xb[a] = Xb[tj + 16 * a][kk];
             }
 #pragma unroll
             for (int a = 0; a < GR_MAXB; ++a)
@@ -597,7 +785,7 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(const double *__restr
 #pragma unroll
         for (int b = 0; b < GR_MAXB; ++b) {
             int r = ti + 16 * a, c = tj + 16 * b;
-            if (r < R && c < R) P[r * R + c] = acc[a][b];
+            if (r < Ra && c < Rb) P[(size_t)(r0 + r) * R + c0 + c] = acc[a][b];
         }
 }
 
@@ -611,10 +799,12 @@ __global__ void __launch_bounds__(kThreads) gram_reduce_kernel(const double *__r
 }
 
 void launch_gram(const double *X, int R, size_t K, double *partials, int nchunks, double *G, hipStream_t s) {
+    if (R <= 0 || R > GR_MAXR) return;  // the host checks R (engine: at most 169)
     size_t chunk = (K + nchunks - 1) / nchunks;
     chunk = (chunk + GR_KB - 1) / GR_KB * GR_KB;
     int used = (int)((K + chunk - 1) / chunk);
-    gram_partial_kernel<<<used, 256, 0, s>>>(X, R, K, chunk, partials);
+    const int ntile = (R + GR_TILE - 1) / GR_TILE;
+    gram_partial_kernel<<<dim3(used, ntile * ntile), 256, 0, s>>>(X, R, K, chunk, ntile, partials);
     gram_reduce_kernel<<<grid_for((size_t)R * R), kThreads, 0, s>>>(partials, R * R, used, G);
 }
 

@@ -56,6 +56,7 @@ class Config(C.Structure):
         ("free", FREE_FN),
         ("alloc_ctx", C.c_void_p),
         ("mem_budget", C.c_size_t),
+        ("dense_only", C.c_int),
     ]
 
 
@@ -79,6 +80,7 @@ class Obs(C.Structure):
         ("device_bytes", C.c_size_t),
         ("eig_sweeps", C.c_int),
         ("eig_residual", C.c_double),
+        ("block_sparse", C.c_int),
     ]
 
     def as_dict(self):
@@ -87,7 +89,7 @@ class Obs(C.Structure):
                     last_axis=self.last_axis, last_side=tuple(self.last_side), last_k=tuple(self.last_k),
                     last_eps=tuple(self.last_eps), min_cut_gap=self.min_cut_gap, flagged=self.flagged,
                     last_cn=self.last_cn, device_bytes=self.device_bytes, eig_sweeps=self.eig_sweeps,
-                    eig_residual=self.eig_residual)
+                    eig_residual=self.eig_residual, block_sparse=self.block_sparse)
 
 
 _lib = None
@@ -218,7 +220,8 @@ class Context:
 
     def __init__(self, beta: float, h: float, dcut: int, precision: int = FP64, impurities: bool = True,
                  keep_checkpoints: bool = False, mixed_from_step: int = 0, tau_deg: float = 0.0, stream=None,
-                 slice_budget: int = 0, eig_max_sweeps: int = 0, mem_budget: int = 0, allocator="torch"):
+                 slice_budget: int = 0, eig_max_sweeps: int = 0, mem_budget: int = 0, allocator="torch",
+                 dense_only: bool = False):
         lib = load()
         self._h = C.c_void_p()
         stream = stream if stream is not None else _current_stream()
@@ -232,6 +235,7 @@ class Context:
         if allocator is not None:
             cfg.alloc, cfg.free = allocator.alloc_fn, allocator.free_fn
         cfg.mem_budget = mem_budget
+        cfg.dense_only = int(dense_only)
         self.beta, self.h, self.dcut = beta, h, dcut
         self.impurities = impurities
         _check(lib.hotrg_init_ex(beta, h, dcut, C.byref(cfg), C.byref(self._h)))

@@ -45,3 +45,26 @@ def sample_indices(shape, count, seed=SEED + 2):
     total = int(np.prod(shape))
     flat = np.sort(rng.choice(total, size=min(count, total), replace=False))
     return [tuple(int(v) for v in np.unravel_index(f, shape)) for f in flat]
+
+
+def z2_isometry(D, k, seed=SEED + 3):
+    """D^2 x k matrix with orthonormal columns, each column supported on the
+    merged rows (i1, i2) of one parity (i1 + i2) mod 2 (parity of bond index
+    i is i mod 2): the shape of an isometry of the h = 0 flow.  Columns of the
+    two parities are interleaved in a random order."""
+    rng = np.random.default_rng(seed)
+    n = D * D
+    rows = [np.array([r for r in range(n) if ((r // D) + (r % D)) % 2 == p]) for p in (0, 1)]
+    k0 = min(len(rows[0]), (k + 1) // 2)
+    k1 = k - k0
+    if k1 > len(rows[1]):
+        k1 = len(rows[1])
+        k0 = k - k1
+    U = np.zeros((n, k))
+    cols = rng.permutation(k)
+    for p, kp, cs in ((0, k0, cols[:k0]), (1, k1, cols[k0:])):
+        if kp == 0:
+            continue
+        q, _ = np.linalg.qr(rng.standard_normal((len(rows[p]), kp)))
+        U[np.ix_(rows[p], cs)] = q
+    return U

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("beta,h,dcut", [(-0.1, 0.0, 4), (float("nan"), 0.0, 4), (0.1, float("inf"), 4),
-                                          (0.1, 0.0, 0), (0.1, 0.0, 13)])
+                                          (0.1, 0.0, 0), (0.1, 0.0, 14)])
 def test_init_rejects_bad_arguments_without_a_device(beta, h, dcut):
     from paper_1906_06060_amd import hotrg
     lib = hotrg.load()
@@ -63,15 +63,16 @@ def test_struct_layouts_match_the_header(tmp_path):
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "hotrg.h"\n'
         "int main(void) {\n"
-        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(hotrg_config), offsetof(hotrg_config, eig_max_sweeps),\n'
+        '  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hotrg_config), offsetof(hotrg_config, eig_max_sweeps),\n'
         "         offsetof(hotrg_config, alloc), offsetof(hotrg_config, mem_budget), sizeof(hotrg_obs),\n"
-        "         offsetof(hotrg_obs, eig_residual));\n"
+        "         offsetof(hotrg_obs, block_sparse), offsetof(hotrg_config, dense_only));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [C.sizeof(hotrg.Config), hotrg.Config.eig_max_sweeps.offset, hotrg.Config.alloc.offset,
-            hotrg.Config.mem_budget.offset, C.sizeof(hotrg.Obs), hotrg.Obs.eig_residual.offset]
+            hotrg.Config.mem_budget.offset, C.sizeof(hotrg.Obs), hotrg.Obs.block_sparse.offset,
+            hotrg.Config.dense_only.offset]
     assert got == want
 
 
