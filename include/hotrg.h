@@ -171,6 +171,24 @@ int hotrg_backward(hotrg_ctx *ctx, double *dlnz_dbeta, double *dlnz_dh);
 void hotrg_free(hotrg_ctx *ctx);
 const char *hotrg_last_error(void);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * observables of hotrg_observables for device tensors the caller holds, with
+ * no context and no allocation.  T (and S_m, S_e, both or neither) are device
+ * pointers to rank-8 FP64 tensors of dims D_q in canonical leg order; `axis`
+ * is the axis of X (Eqs. (3.2)-(3.3)); n and lnz_acc give lnZ/N = lnz_acc +
+ * 2^-n ln Tr T; h enters e_imp.  out gets n, dims, lnz_per_site, trace, m_imp,
+ * nn_imp, e_imp (NaN without impure tensors), X and last_axis = axis; the
+ * decision fields are empty (last_side -1, min_cut_gap inf, the rest 0).
+ * Work is enqueued on `stream` (hipStream_t, NULL = default) and the call
+ * waits for it.  The trace kernel's partial results go to a fixed device
+ * array of 3 + 13^2 doubles per GPU, owned by the library for the life of the
+ * process: bond dimensions above 13 give HOTRG_EINVAL.  Calls that overlap on
+ * one GPU (other threads, other streams) share that array and race; each call
+ * overwrites every entry it reads.  Errors: HOTRG_EINVAL (arguments),
+ * HOTRG_EDEVICE (a HIP call failed). */
+int hotrg_observables_noalloc(const double *T, const double *Sm, const double *Se, const int dims[4], int axis,
+                              double h, int n, double lnz_acc, void *stream, hotrg_obs *out);
 
 /* ---- state access for parity tests and checkpoint/resume ------------------ */
 

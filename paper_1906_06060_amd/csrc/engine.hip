@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1948,7 +1949,7 @@ int backward(hotrg_ctx *c, double *dbeta, double *dh) {
 
 // Observables from the traces of Eq. (2.5) and the A matrix of Eq. (3.2)
 // (Da x Da): ln Z / N, the impurity ratios of Eqs. (2.10), (2.12), and X of
-// Eq. (3.3).
+// Eq. (3.3).  Shared by hotrg_observables and hotrg_observables_noalloc.
 void obs_from_traces(double tr, double trm, double tre, const double *A, int Da, int n, double lnz_acc, double h,
                      bool imp, hotrg_obs *o) {
     // a state set by the caller may have Tr <= 0; ln Z is then undefined (NaN)
@@ -1969,8 +1970,73 @@ void obs_from_traces(double tr, double trm, double tre, const double *A, int Da,
     o->X = trA * trA / trA2;
 }
 
+// ---- scratch of the no-allocation entry point ------------------------------
+// Device memory for the trace kernel's partial results (the three traces and
+// the A matrix) when the caller cannot allocate: one file-scope array per
+// GPU, alive until the process ends.  Host code never uses the array's name
+// as an address: the device address comes from hipGetSymbolAddress, once per
+// device (with that device current), and is kept in g_scratch_ptr.
+constexpr int kNoallocMaxDim = 13;
+constexpr int kScratchDoubles = 3 + kNoallocMaxDim * kNoallocMaxDim;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_err(HOTRG_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return set_err(HOTRG_EDEVICE, "device id out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_err(HOTRG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HOTRG_OK;
+}
+
 // =============================================================== C ABI ====
 extern "C" {
+
+int hotrg_observables_noalloc(const double *T, const double *Sm, const double *Se, const int dims[4], int axis,
+                              double h, int n, double lnz_acc, void *stream, hotrg_obs *out) {
+    if (!T || !dims || !out) return set_err(HOTRG_EINVAL, "null argument");
+    if (axis < 0 || axis > 3) return set_err(HOTRG_EINVAL, "axis must be 0..3");
+    if (n < 0 || !std::isfinite(h) || !std::isfinite(lnz_acc)) return set_err(HOTRG_EINVAL, "bad n, h or lnz_acc");
+    if ((Sm == nullptr) != (Se == nullptr)) return set_err(HOTRG_EINVAL, "give both impure tensors or neither");
+    for (int q = 0; q < 4; ++q)
+        if (dims[q] < 1 || dims[q] > kNoallocMaxDim)
+            return set_err(HOTRG_EINVAL, "hotrg_observables_noalloc: bond dimensions must be in 1.." +
+                                             std::to_string(kNoallocMaxDim) + " (scratch holds " +
+                                             std::to_string(kScratchDoubles) + " doubles)");
+    double *sp = nullptr;
+    TRY(scratch_for_current_device(&sp));
+    hipStream_t st = (hipStream_t)stream;
+    launch_trace_obs(T, Sm, Se, dims, axis, sp, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(HOTRG_EDEVICE, std::string("trace kernel: ") + hipGetErrorString(e));
+    const int Da = dims[axis];
+    double hbuf[kScratchDoubles];
+    e = hipMemcpyAsync(hbuf, sp, sizeof(double) * (3 + (size_t)Da * Da), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_err(HOTRG_EDEVICE, std::string("scratch copy: ") + hipGetErrorString(e));
+    std::memset(out, 0, sizeof(*out));
+    out->n = n;
+    for (int q = 0; q < 4; ++q) {
+        out->dims[q] = dims[q];
+        out->last_side[q] = -1;
+    }
+    obs_from_traces(hbuf[0], hbuf[1], hbuf[2], hbuf + 3, Da, n, lnz_acc, h, Sm != nullptr, out);
+    out->last_axis = axis;
+    out->min_cut_gap = INFINITY;
+    return HOTRG_OK;
+}
 
 const char *hotrg_last_error(void) { return g_err.c_str(); }
 

@@ -25,7 +25,7 @@ EXPORTS = (
     "hotrg_init", "hotrg_init_ex", "hotrg_step", "hotrg_lnZ", "hotrg_observables",
     "hotrg_backward", "hotrg_free", "hotrg_last_error", "hotrg_get_dims", "hotrg_get_tensor",
     "hotrg_set_state", "hotrg_truncate", "hotrg_step_with_isometries", "hotrg_get_isometry",
-    "hotrg_get_spectrum", "hotrg_kernel_stats", "hotrg_reset_stats",
+    "hotrg_get_spectrum", "hotrg_kernel_stats", "hotrg_reset_stats", "hotrg_observables_noalloc",
 )
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -131,6 +131,8 @@ def load(path: str = LIB_PATH):
         "hotrg_get_spectrum": ([P, C.c_int, C.c_int, dp, C.c_size_t, ip], C.c_int),
         "hotrg_kernel_stats": ([P, C.c_int, dp, C.POINTER(C.c_longlong), dp], C.c_int),
         "hotrg_reset_stats": ([P], C.c_int),
+        "hotrg_observables_noalloc": ([P, P, P, ip, C.c_int, C.c_double, C.c_int, C.c_double, P,
+                                       C.POINTER(Obs)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -343,6 +345,19 @@ class Context:
 
     def reset_stats(self):
         _check(_lib.hotrg_reset_stats(self._h))
+
+
+def observables_noalloc(T_ptr: int, dims, axis: int, h: float = 0.0, n: int = 0, lnz_acc: float = 0.0,
+                        Sm_ptr: int = 0, Se_ptr: int = 0, stream=None) -> dict:
+    """hotrg_observables_noalloc on caller-held device tensors (raw device
+    pointers, e.g. torch tensors' data_ptr()); allocates nothing on the device."""
+    lib = load()
+    o = Obs()
+    d = (C.c_int * 4)(*dims)
+    st = stream if stream is not None else _current_stream()
+    _check(lib.hotrg_observables_noalloc(C.c_void_p(T_ptr), C.c_void_p(Sm_ptr or None), C.c_void_p(Se_ptr or None),
+                                         d, axis, h, n, lnz_acc, st, C.byref(o)))
+    return o.as_dict()
 
 
 def flow(beta: float, h: float, dcut: int, nsteps: int, axes=None, **kw):
