@@ -26,8 +26,8 @@ PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
 # HBM bytes per GEMM call (main + tail dispatch + fix-up) of the bf16x3 GEMM at this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # plain 2 GiB copy); valid only while the kernel source is the one profiled.
-GEMM_TRAFFIC_BYTES = {("dense", 10, True, True): 311375665375}
-GEMM_TRAFFIC_SRC_SHA = "bd6bbd792c297d0c"
+GEMM_TRAFFIC_BYTES = {("z2", 10, True, True): 72359328728}
+GEMM_TRAFFIC_SRC_SHA = "5564fef28b45ecad"
 
 
 BF16X3_SECTION = "// ---------------------------------------------------------------- bf16x3 ---"
@@ -486,9 +486,13 @@ def main():
             "traffic_unit": "bytes per GEMM call (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "launches": st["launches"],
             "avg_launch_ms": round(st["ms"] / max(st["launches"], 1), 3),
-            "launch": ("one GEMM call per K slice: a main dispatch over whole rounds of tiles, a tail dispatch "
-                       "running the last partial round as k-halves, and gemm_tail_fixup_kernel"
-                       if prec == H.BF16X3 else "one gemm_f64_kernel dispatch per K slice"),
+            "launch": (("one GEMM call per K slice covering both parity classes' products as one tile list: "
+                        if block else "one GEMM call per K slice: ") +
+                       "a main dispatch over whole rounds of tiles, a tail dispatch running the last partial "
+                       "round as k-halves, and gemm_tail_fixup_kernel"
+                       if prec == H.BF16X3 else
+                       ("two gemm_f64_kernel dispatches per K slice (one per parity class)" if block
+                        else "one gemm_f64_kernel dispatch per K slice")),
         },
     }
     n_ph = max(ph["steps"], 1)
