@@ -666,6 +666,10 @@ int z2_scatter(hotrg_ctx *c, XP &x, uint64_t Ks, uint32_t zs, uint32_t zP, const
         if (run && kmax < Ks) {
             p.z2 = 2;
             p.zrs = (uint32_t)(p.o1 / Ks);
+            // pairs: the second loop walks adjacent K indices, and the hi / lo
+            // blocks are 4-byte aligned
+            p.zpair = mixed && p.o2 == 1 && ((uintptr_t)hi[0] & 3) == 0 && ((uintptr_t)hi[1] & 3) == 0 &&
+                      ((uintptr_t)lo[0] & 3) == 0 && ((uintptr_t)lo[1] & 3) == 0;
         }
     }
     p.zld = make_fastdiv((uint32_t)Ks);

@@ -72,6 +72,8 @@ struct ExpandParams {
     // (o2 < zld and no carry out of the K part), so a thread needs one row
     // and N K lookups
     uint32_t zrs;
+    int zpair;  // run form, bf16: the second loop steps one K position (o2 == 1), so
+                // consecutive outputs of a run may go out as 4-byte pairs
     FastDiv zld;
     const uint32_t *rtab, *ktab;
     uint32_t zs, zP;

@@ -353,6 +353,12 @@ __global__ void __launch_bounds__(kThreads) iso_expand_z2run_kernel(ExpandParams
             uint16_t *hi = SPLIT ? p.zhi[blk] : nullptr;
             uint16_t *lo = SPLIT ? p.zlo[blk] : nullptr;
             double *out = SPLIT ? nullptr : p.zout[blk];
+            // bf16: an output at an even column whose successor in the run is
+            // the next column goes out with it as one 4-byte (hi, hi') and one
+            // (lo, lo') store (both in one 32-k piece of the packed row)
+            bool held = false;
+            uint32_t hcol = 0;
+            uint16_t hh = 0, hl = 0;
 #pragma unroll
             for (int l2 = 0; l2 < N; ++l2) {
                 if ((kt[l2] >> 31) != blk) continue;  // structurally zero
@@ -362,12 +368,38 @@ __global__ void __launch_bounds__(kThreads) iso_expand_z2run_kernel(ExpandParams
                 const uint32_t col = kt[l2] & ~Z2_PAR;
                 if (SPLIT) {
                     const uint16_t h = bf16_bits((float)acc);
-                    const size_t po = rbase + (size_t)(col / PACK_K) * (PACK_ROWS * PACK_K) + col % PACK_K;
-                    hi[po] = h;
-                    lo[po] = bf16_bits((float)(acc - bf16_value(h)));
+                    const uint16_t l = bf16_bits((float)(acc - bf16_value(h)));
+                    if (held && col == hcol + 1) {
+                        const size_t po = rbase + (size_t)(hcol / PACK_K) * (PACK_ROWS * PACK_K) + hcol % PACK_K;
+                        *(uint32_t *)(hi + po) = (uint32_t)hh | ((uint32_t)h << 16);
+                        *(uint32_t *)(lo + po) = (uint32_t)hl | ((uint32_t)l << 16);
+                        held = false;
+                        continue;
+                    }
+                    if (held) {
+                        const size_t po = rbase + (size_t)(hcol / PACK_K) * (PACK_ROWS * PACK_K) + hcol % PACK_K;
+                        hi[po] = hh;
+                        lo[po] = hl;
+                        held = false;
+                    }
+                    if ((col & 1) == 0 && p.zpair) {
+                        held = true;
+                        hcol = col;
+                        hh = h;
+                        hl = l;
+                    } else {
+                        const size_t po = rbase + (size_t)(col / PACK_K) * (PACK_ROWS * PACK_K) + col % PACK_K;
+                        hi[po] = h;
+                        lo[po] = l;
+                    }
                 } else {
                     out[rbase + col] = acc;
                 }
+            }
+            if (SPLIT && held) {
+                const size_t po = rbase + (size_t)(hcol / PACK_K) * (PACK_ROWS * PACK_K) + hcol % PACK_K;
+                hi[po] = hh;
+                lo[po] = hl;
             }
         }
     }
