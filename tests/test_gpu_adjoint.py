@@ -135,8 +135,7 @@ def test_autograd_function_gives_energy_and_magnetisation(H):
     assert magnetisation == pytest.approx(th[2] / beta0, rel=1e-8)
 
 
-@pytest.mark.parametrize("h", [0.0, 1e-4])
-@pytest.mark.parametrize("beta", [0.1480, 0.1497, 0.1510])
+@pytest.mark.parametrize("beta,h", [(0.1497, 0.0), (0.1497, 1e-4), (0.1510, 0.0)])
 def test_backward_dcut8_against_central_differences(H, beta, h):
     # the forward-plus-adjoint configuration at Dcut = 8 (FP64; 6 steps, so
     # steps 4-6 run at dims 8^4 with 64 x 64 eigenproblems): E = -dlnZ/dbeta

@@ -363,7 +363,7 @@ def test_truncate_full_size_matches_oracle(H, D, axis):
                 sg = ctx.spectrum(q, side)
                 so = dec.spectra[side]
                 assert len(sg) == D * D
-                np.testing.assert_allclose(sg / so[0], so / so[0], rtol=0, atol=1e-13)
+                np.testing.assert_allclose(sg / so[0], so / so[0], rtol=0, atol=1e-12)
             assert ob["last_side"][q] == dec.side
             assert ob["last_k"][q] == dec.k
             Ug = ctx.isometry(q)
@@ -379,7 +379,10 @@ def test_flow_dcut8_matches_stored_values(H):
     # 64 x 64 environments) against tests/golden/dcut8_beta01497_h1e-5_6steps.json,
     # written from the oracle by tests/golden/make_golden.py: c_n and lnZ/N to
     # 1e-10 relative, impurity e, m and X to 1e-8, dims, kept k and chosen
-    # side exactly, the chosen environment spectra to 1e-13 lam_1
+    # side exactly, the chosen environment spectra to 1e-12 lam_1 (Weyl: an
+    # eigenvalue moves by at most ||dE||_2; E is quartic in T, whose FP64
+    # rounding after three truncated steps with sums of 8^7 terms is a few
+    # 1e-13 relative)
     import json
     import os
     gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
@@ -399,7 +402,7 @@ def test_flow_dcut8_matches_stored_values(H):
                 assert g["last_side"][d["axis"]] == d["side"]
                 so = np.array(d["spectrum"])
                 sg = ctx.spectrum(d["axis"], d["side"])
-                np.testing.assert_allclose(sg / so[0], so / so[0], rtol=0, atol=1e-13)
+                np.testing.assert_allclose(sg / so[0], so / so[0], rtol=0, atol=1e-12)
 
 
 # ----------------- D = 10 sampled contraction, 64 x 64 entries ----
