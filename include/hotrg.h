@@ -236,7 +236,12 @@ int hotrg_get_spectrum(hotrg_ctx *ctx, int q, int side, double *out, size_t coun
  * and GEMMs) and after the normalisation and permutation: 1 = isometries,
  * 2 = contraction (flops = the GEMM flops), 3 = normalisation; launches = steps
  * counted.  Phase times include device idle time while the host decides the
- * cut.  Querying a phase waits for the last step to finish. */
+ * cut.  Querying a phase waits for the last step to finish.
+ * kernel 4: launches = how many last isometry products of Z2 block-form
+ * steps wrote their bf16 operand blocks through LDS tiles in whole 16-byte
+ * pieces (the rest scatter element by element; the environment variable
+ * HOTRG_Z2_TILE=0 selects that for every launch; both give identical bits);
+ * ms = flops = 0. */
 int hotrg_kernel_stats(hotrg_ctx *ctx, int kernel, double *ms, long long *launches, double *flops);
 int hotrg_reset_stats(hotrg_ctx *ctx);
 

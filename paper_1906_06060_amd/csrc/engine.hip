@@ -111,6 +111,15 @@ struct hotrg_ctx {
     size_t ev_used = 0;
     double gemm_ms = 0;
     long long gemm_launches = 0;
+    long long z2_tile_launches = 0;  // last isometry products run in the tile form of the Z2 scatter
+    // tile form of the Z2 scatter, per last product (0: A rows, 1: B rows):
+    // the slot table and the permuted isometry block, rebuilt once per set of
+    // class tables (z2_gen counts build_z2_tables calls)
+    long long z2_gen = 0, tile_gen[2] = {-1, -1};
+    std::vector<uint32_t> tperm_h[2];
+    uint32_t *tperm_d[2] = {nullptr, nullptr};
+    double *tU_d[2] = {nullptr, nullptr};
+    uint32_t tslots[2] = {0, 0};
     double gemm_flops = 0;
     size_t device_bytes = 0;
     // phase timing of hotrg_step: events at the start, after the isometries,
@@ -580,7 +589,7 @@ int isometries(hotrg_ctx *c, const double *T, const uint64_t lst[8], const int l
 
 // Parity class tables of a Z2 block-form step (see ExpandParams): rows (and
 // columns) (a, b, mu1, c) of the GEMM with the new labels of the transverse
-// axes and the mu labels, inner K indices (b1', c1', a2, b2, c2) of a slice
+// axes and the mu labels, inner K indices (b1', a2, c1', b2, c2) of a slice
 // with the old labels (b1' counted in the slice parity when a slice fixes
 // it).  Positions count each class in natural order.  Also fills the block
 // sizes: R_g = N_g (pure T) or N_g + N_{1-g} + N_g (T | S_m | S_e).
@@ -605,13 +614,16 @@ int build_z2_tables(hotrg_ctx *c, int mu, const int tv[3], const int k[3], int E
                     const int p = pa[a] ^ pb[b] ^ pm[m] ^ pc[cc];
                     rt[r++] = (p ? Z2_PAR : 0u) | cnt[p]++;
                 }
+    // (the block form orders a slice's inner K indices as (b1', a2, c1', b2,
+    // c2): a2 outside c1', so that both last products cover whole K runs per
+    // (b1', a2), see contract())
     const uint32_t Ks = (uint32_t)Eb * Dc * Da * Db * Dc;
     auto &kt = c->ktab_h;
     kt.resize(Ks);
     uint32_t kcnt[2] = {0, 0}, kk = 0;
     for (int b1 = 0; b1 < Eb; ++b1)
-        for (int c1 = 0; c1 < Dc; ++c1)
-            for (int a2 = 0; a2 < Da; ++a2)
+        for (int a2 = 0; a2 < Da; ++a2)
+            for (int c1 = 0; c1 < Dc; ++c1)
                 for (int b2 = 0; b2 < Db; ++b2)
                     for (int c2 = 0; c2 < Dc; ++c2) {
                         const int p = (Eb == Db ? ob[b1] : 0) ^ oc[c1] ^ oa[a2] ^ ob[b2] ^ oc[c2];
@@ -631,15 +643,133 @@ int build_z2_tables(hotrg_ctx *c, int mu, const int tv[3], const int k[3], int E
     if (!c->ktab) TRY(alloc_n(c, &c->ktab, Dmax * Dmax * Dmax * Dmax * Dmax));
     HIP_TRY(c, hipMemcpyAsync(c->rtab, rt.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->ktab, kt.data(), sizeof(uint32_t) * Ks, hipMemcpyHostToDevice, c->stream));
+    c->z2_gen++;
+    return HOTRG_OK;
+}
+
+// Tile form of the bf16 Z2 scatter (see ExpandParams): whether the thread
+// dims of x are [nko K-outer | nro row | inner] with the K-outer dims a dense
+// row-major walk over K groups of tnK indices, the row dims a dense walk over
+// units of L1 rows, and the inner dims plus the second loop a dense run of
+// tnK K indices, and the first loop one row per step.  Fills the tile fields
+// (the slot table and the permuted isometry block `id` are rebuilt when the
+// class tables changed) and returns false, so that the run form is used,
+// when the layout does not match or a limit is exceeded.
+int z2_tile_plan(hotrg_ctx *c, ExpandParams &p, const double *U, uint64_t threads, int nko, int nro, uint64_t Ks,
+                 int id, bool *ok) {
+    *ok = false;
+    if (id < 0 || id > 1 || nko < 0 || nro < 0 || nko + nro > p.nd || p.o1 != Ks) return HOTRG_OK;
+    if (const char *e = getenv("HOTRG_Z2_TILE"))
+        if (e[0] == '0') return HOTRG_OK;
+    // inner dims and the second loop: a dense run [0, nK)
+    std::vector<std::pair<uint64_t, uint64_t>> in;  // (stride, extent)
+    uint64_t P = 1;
+    for (int d = nko + nro; d < p.nd; ++d) {
+        P *= p.ext[d].d;
+        if (p.ext[d].d > 1) in.push_back({p.out_st[d], p.ext[d].d});
+    }
+    if (p.L2 > 1) in.push_back({p.o2, (uint64_t)p.L2});
+    std::sort(in.begin(), in.end());
+    uint64_t nK = 1;
+    for (const auto &se : in) {
+        if (se.first != nK) return HOTRG_OK;
+        nK *= se.second;
+    }
+    // K-outer dims: groups K0 = kg nK, kg < Kg, Kg nK = Ks
+    uint64_t st = nK, Kg = 1;
+    for (int d = nko - 1; d >= 0; --d) {
+        if (p.ext[d].d > 1 && p.out_st[d] != st) return HOTRG_OK;
+        st *= p.ext[d].d;
+        Kg *= p.ext[d].d;
+    }
+    if (st != Ks) return HOTRG_OK;
+    // row dims: unit u starts at row u L1
+    uint64_t rs = Ks * (uint64_t)p.L1, NRP = 1;
+    for (int d = nko + nro - 1; d >= nko; --d) {
+        if (p.ext[d].d > 1 && p.out_st[d] != rs) return HOTRG_OK;
+        rs *= p.ext[d].d;
+        NRP *= p.ext[d].d;
+    }
+    if (P == 0 || NRP * Kg * P != threads) return HOTRG_OK;
+    const auto &kt = c->ktab_h;
+    if (kt.size() != Ks) return HOTRG_OK;
+    // largest class share of one K group
+    uint64_t maxnk = 0;
+    for (uint64_t g = 0; g < Kg; ++g) {
+        uint64_t n1 = 0;
+        for (uint64_t k = g * nK; k < (g + 1) * nK; ++k) n1 += kt[k] >> 31;
+        maxnk = std::max(maxnk, std::max(n1, nK - n1));
+    }
+    // slot table: inner threads by the class of their first K index in the
+    // first K group (the class of every K index of a thread's run in any group
+    // is that class xor a label of the loop index xor the group's parity, so
+    // one parity per wave stays one parity in every group), each class padded
+    // to whole waves
+    if (c->tile_gen[id] != c->z2_gen) {
+        std::vector<uint32_t> cls[2];
+        for (uint64_t j = 0; j < P; ++j) {
+            uint64_t rem = j, k0 = 0;
+            for (int d = p.nd - 1; d >= nko + nro; --d) {
+                k0 += (rem % p.ext[d].d) * p.out_st[d];
+                rem /= p.ext[d].d;
+            }
+            cls[kt[k0] >> 31].push_back((uint32_t)j);
+        }
+        auto &tp = c->tperm_h[id];
+        tp.clear();
+        for (int q = 0; q < 2; ++q) {
+            const size_t padded = (cls[q].size() + 63) / 64 * 64;
+            tp.insert(tp.end(), cls[q].begin(), cls[q].end());
+            tp.insert(tp.end(), padded - cls[q].size(), ~0u);
+        }
+        if (tp.size() > (size_t)Z2TILE_MAX_THREADS) return HOTRG_OK;
+        c->tslots[id] = (uint32_t)tp.size();
+        if (!c->tperm_d[id]) TRY(alloc_n(c, &c->tperm_d[id], (size_t)Z2TILE_MAX_THREADS));
+        if (!c->tU_d[id]) TRY(alloc_n(c, &c->tU_d[id], (size_t)13 * 13 * 13));
+        HIP_TRY(c, hipMemcpyAsync(c->tperm_d[id], tp.data(), sizeof(uint32_t) * tp.size(), hipMemcpyHostToDevice,
+                                  c->stream));
+        c->tile_gen[id] = c->z2_gen;
+    }
+    // the isometry block in use order [l1][l2][i] (a tiny gather, every call:
+    // the two A / B products of a step share it, S_m / S_e reuse it)
+    if ((uint64_t)p.L1 * p.L2 * p.nsum > 13 * 13 * 13) return HOTRG_OK;
+    {
+        PermParams pp{};
+        pp.nd = 3;
+        const uint32_t e3[3] = {(uint32_t)p.L1, (uint32_t)p.L2, (uint32_t)p.nsum};
+        const uint32_t s3[3] = {p.u1, p.u2, p.us};
+        for (int k = 0; k < 3; ++k) {
+            pp.ext[k] = make_fastdiv(e3[k]);
+            pp.in_st[k] = s3[k];
+        }
+        pp.total = e3[0] * e3[1] * e3[2];
+        launch_permute(pp, U, c->tU_d[id], 1.0, c->stream);
+    }
+    p.tslots = c->tslots[id];
+    p.tperm = c->tperm_d[id];
+    p.tU = c->tU_d[id];
+    p.tLD = (uint32_t)((maxnk + 7 + 7) / 8 * 8);
+    p.tP = (uint32_t)P;
+    p.tNRP = (uint32_t)NRP;
+    p.tKg = (uint32_t)Kg;
+    p.tnK = (uint32_t)nK;
+    // units per tile: at most Z2TILE_MAX_THREADS threads and about 40 KB of tiles
+    const uint64_t unit_bytes = (uint64_t)p.L1 * p.tLD * 4;
+    uint64_t upb = std::min<uint64_t>(Z2TILE_MAX_THREADS / p.tslots, std::max<uint64_t>(1, 40960 / unit_bytes));
+    p.tupb = (uint32_t)std::max<uint64_t>(1, std::min(upb, NRP));
+    *ok = z2tile_lds_bytes(p) <= Z2TILE_MAX_LDS;
     return HOTRG_OK;
 }
 
 // Turns the last isometry product described by x into the Z2 block scatter
 // (natural row length Ks, slice parity zs, tensor parity zP, first rows off[g]
 // of the tensor in class g) into the blocks out / hi / lo, with host checks
-// that every write stays inside its block.
-int z2_scatter(hotrg_ctx *c, XP &x, uint64_t Ks, uint32_t zs, uint32_t zP, const uint32_t off[2], uint64_t rows_cap,
-               bool mixed, double *const out[2], uint16_t *const hi[2], uint16_t *const lo[2]) {
+// that every write stays inside its block.  For bf16 outputs whose thread
+// dims are laid out as [nko K-outer | nro row | inner] (see z2_tile_plan) the
+// tile form is used.
+int z2_scatter(hotrg_ctx *c, XP &x, const double *U, uint64_t Ks, uint32_t zs, uint32_t zP, const uint32_t off[2],
+               uint64_t rows_cap, bool mixed, double *const out[2], uint16_t *const hi[2], uint16_t *const lo[2],
+               int nko = -1, int nro = -1, int tile_id = -1) {
     ExpandParams &p = x.p;
     const auto &zl = c->z2l;
     if (p.nsum != p.L2 || p.L2 > 13 || (size_t)p.L1 * p.L2 * p.L2 * sizeof(double) > 48 * 1024)
@@ -672,11 +802,24 @@ int z2_scatter(hotrg_ctx *c, XP &x, uint64_t Ks, uint32_t zs, uint32_t zP, const
                       ((uintptr_t)lo[0] & 3) == 0 && ((uintptr_t)lo[1] & 3) == 0;
         }
     }
+    if (mixed && p.z2 == 2 && (((uintptr_t)hi[0] | (uintptr_t)hi[1] | (uintptr_t)lo[0] | (uintptr_t)lo[1]) & 15) == 0) {
+        bool ok = false;
+        TRY(z2_tile_plan(c, p, U, x.threads, nko, nro, Ks, tile_id, &ok));
+        if (ok) {
+            p.z2 = 3;
+            c->z2_tile_launches++;
+        }
+    }
     p.zld = make_fastdiv((uint32_t)Ks);
     p.rtab = c->rtab;
     p.ktab = c->ktab;
     p.zs = zs;
     p.zP = zP;
+    p.zM = (uint32_t)c->rtab_h.size();
+    for (int b = 0; b < 2; ++b) {
+        p.zKc[b] = zl.Kc[b];
+        p.zNr[b] = zl.N[b];
+    }
     for (int b = 0; b < 2; ++b) {
         p.zrow_off[b] = off[b];
         p.zld_out[b] = (uint32_t)zl.ldk[b];
@@ -824,9 +967,13 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     uint64_t z2s[8];
     row_major_strides(8, z2e, z2s);
 
-    // K-part strides of an operand row (b1', c1', a2, b2, c2) and row strides
-    const uint64_t ks0 = (uint64_t)Dc * Da * Db * Dc, ks1 = (uint64_t)Da * Db * Dc, ks2 = (uint64_t)Db * Dc,
-                   ks3 = Dc;
+    // K-part strides of an operand row: (b1', c1', a2, b2, c2) in the dense
+    // form, (b1', a2, c1', b2, c2) in the block form (the order of ktab); and
+    // row strides
+    const uint64_t kb1 = (uint64_t)Dc * Da * Db * Dc;
+    const uint64_t kc1 = z2 ? (uint64_t)Db * Dc : (uint64_t)Da * Db * Dc;
+    const uint64_t ka2 = z2 ? (uint64_t)Dc * Db * Dc : (uint64_t)Db * Dc;
+    const uint64_t kb2 = Dc;
     // (the Z2 scatter splits natural offsets r Ks + k, so its row length is Ks)
     const uint64_t ldn = z2 ? Ks : ld;
     const uint64_t rs0 = (uint64_t)kb * Dm * kc * ldn, rs1 = (uint64_t)Dm * kc * ldn, rs2 = (uint64_t)kc * ldn;
@@ -872,13 +1019,23 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                 }
                 {   // P3: A[(a,b,mu1,c),(b1',c1',a2,b2,c2)] = sum_c1 Uc[(c1,c2),c] Y2
                     XP x;
-                    x.tdim(ka, y2s[0], rs0);
-                    x.tdim(kb, y2s[1], rs1);
-                    x.tdim(Dm, y2s[2], rs2);
-                    x.tdim(Eb, y2s[3], ks0);
-                    x.tdim(Dc, y2s[4], ks1);
-                    x.tdim(Da, y2s[5], ks2);
-                    x.tdim(Db, y2s[6], ks3);
+                    if (z2) {  // tile layout: K-outer (b1', a2), rows (a, b, mu1), inner (c1', b2)
+                        x.tdim(Eb, y2s[3], kb1);
+                        x.tdim(Da, y2s[5], ka2);
+                        x.tdim(ka, y2s[0], rs0);
+                        x.tdim(kb, y2s[1], rs1);
+                        x.tdim(Dm, y2s[2], rs2);
+                        x.tdim(Dc, y2s[4], kc1);
+                        x.tdim(Db, y2s[6], kb2);
+                    } else {
+                        x.tdim(ka, y2s[0], rs0);
+                        x.tdim(kb, y2s[1], rs1);
+                        x.tdim(Dm, y2s[2], rs2);
+                        x.tdim(Eb, y2s[3], kb1);
+                        x.tdim(Dc, y2s[4], kc1);
+                        x.tdim(Da, y2s[5], ka2);
+                        x.tdim(Db, y2s[6], kb2);
+                    }
                     x.loops(kc, 1, ldn, Dc, kc, 1);
                     x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
                     if (!x.fits(c->cap, usz[2], M * ldn)) return set_err(HOTRG_EINVAL, "P3 launch out of bounds");
@@ -887,7 +1044,8 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                         uint32_t off[2];
                         for (int gg = 0; gg < 2; ++gg)
                             off[gg] = t == 0 ? 0u : (t == 1 ? zl.N[gg] : (uint32_t)M);
-                        TRY(z2_scatter(c, x, Ks, zs, t == 1 ? 1u : 0u, off, z2_arows, mixed, zA, zAh, zAl));
+                        TRY(z2_scatter(c, x, Uc, Ks, zs, t == 1 ? 1u : 0u, off, z2_arows, mixed, zA, zAh, zAl, 2, 3,
+                                       0));
                         launch_iso_expand(x.done(), c->y2, Uc, nullptr, nullptr, nullptr, c->stream);
                     } else if (mixed && stack) {  // rows t*M .. t*M + M - 1 of one packed block
                         x.packed(ld, (uint32_t)(t * M));
@@ -934,19 +1092,27 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                 }
                 {   // Q3: Bt[(a',b',mu2',c'),(b1',c1',a2,b2,c2)] = sum_c2' Uc[(c1',c2'),c'] Z2
                     XP x;
-                    x.tdim(ka, z2s[0], rs0);
-                    x.tdim(kb, z2s[1], rs1);
-                    x.tdim(Dm, z2s[2], rs2);
-                    x.tdim(Eb, z2s[3], ks0);
-                    x.tdim(Da, z2s[4], ks2);
-                    x.tdim(Db, z2s[5], ks3);
+                    if (z2) {  // tile layout: K-outer (b1', a2), rows (a', b', mu2'), inner (b2, c2)
+                        x.tdim(Eb, z2s[3], kb1);
+                        x.tdim(Da, z2s[4], ka2);
+                        x.tdim(ka, z2s[0], rs0);
+                        x.tdim(kb, z2s[1], rs1);
+                        x.tdim(Dm, z2s[2], rs2);
+                    } else {
+                        x.tdim(ka, z2s[0], rs0);
+                        x.tdim(kb, z2s[1], rs1);
+                        x.tdim(Dm, z2s[2], rs2);
+                        x.tdim(Eb, z2s[3], kb1);
+                        x.tdim(Da, z2s[4], ka2);
+                    }
+                    x.tdim(Db, z2s[5], kb2);
                     x.tdim(Dc, z2s[6], 1);
-                    x.loops(kc, 1, ldn, Dc, (uint64_t)Dc * kc, ks1);
+                    x.loops(kc, 1, ldn, Dc, (uint64_t)Dc * kc, kc1);
                     x.sum(Dc, z2s[7], kc);
                     if (!x.fits(c->cap, usz[2], M * ldn)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
                     if (z2) {
                         const uint32_t off[2] = {0u, 0u};
-                        TRY(z2_scatter(c, x, Ks, zs, 0u, off, z2_brows, mixed, zB, zBh, zBl));
+                        TRY(z2_scatter(c, x, Uc, Ks, zs, 0u, off, z2_brows, mixed, zB, zBh, zBl, 2, 3, 1));
                         launch_iso_expand(x.done(), c->y2, Uc, nullptr, nullptr, nullptr, c->stream);
                     } else if (mixed) {
                         x.packed(ld);
@@ -2325,11 +2491,17 @@ int hotrg_get_spectrum(hotrg_ctx *c, int q, int side, double *out, size_t count,
 }
 
 int hotrg_kernel_stats(hotrg_ctx *c, int kernel, double *ms, long long *launches, double *flops) {
-    if (!c || kernel < 0 || kernel > 3) return set_err(HOTRG_EINVAL, "bad argument");
+    if (!c || kernel < 0 || kernel > 4) return set_err(HOTRG_EINVAL, "bad argument");
     if (kernel == 0) {
         if (ms) *ms = c->gemm_ms;
         if (launches) *launches = c->gemm_launches;
         if (flops) *flops = c->gemm_flops;
+        return HOTRG_OK;
+    }
+    if (kernel == 4) {
+        if (ms) *ms = 0.0;
+        if (launches) *launches = c->z2_tile_launches;
+        if (flops) *flops = 0.0;
         return HOTRG_OK;
     }
     TRY(flush_phases(c));
@@ -2347,6 +2519,7 @@ int hotrg_reset_stats(hotrg_ctx *c) {
     c->gemm_ms = 0;
     c->gemm_launches = 0;
     c->gemm_flops = 0;
+    c->z2_tile_launches = 0;
     return HOTRG_OK;
 }
 

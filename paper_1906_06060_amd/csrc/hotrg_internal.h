@@ -74,6 +74,22 @@ struct ExpandParams {
     uint32_t zrs;
     int zpair;  // run form, bf16: the second loop steps one K position (o2 == 1), so
                 // consecutive outputs of a run may go out as 4-byte pairs
+    // z2 == 3: the tile form (bf16 only, see iso_expand_z2tile_kernel).  The
+    // thread dims are [K-outer | row | inner]: a unit is one multi-index of
+    // the K-outer and row dims with its tP inner threads; a K group (one
+    // K-outer multi-index) covers the natural K run [K0, K0 + tnK) through
+    // the inner dims and the second loop, and a unit covers L1 consecutive
+    // rows (first loop, one row per step).  A tile is tupb consecutive units
+    // of one K group: a rectangle of natural rows x K indices whose outputs
+    // are gathered in LDS in class order and written as whole 16-byte pieces.
+    uint32_t tP, tNRP, tKg, tupb, tnK;
+    uint32_t tLD;     // LDS row length of a tile (bf16 elements, multiple of 8)
+    uint32_t tslots;  // thread slots per unit (a multiple of 64)
+    const uint32_t *tperm;  // slot -> inner thread (~0u: idle), K-run parity 0 first
+    const double *tU;       // the isometry block as [l1][l2][i] (L1 x L2 x nsum)
+    uint32_t zKc[2];  // K indices of each class (size of ktab = zKc[0] + zKc[1])
+    uint32_t zNr[2];  // rows of each parity (size of rtab = zM)
+    uint32_t zM;
     FastDiv zld;
     const uint32_t *rtab, *ktab;
     uint32_t zs, zP;
@@ -86,6 +102,12 @@ struct ExpandParams {
 // Z2 parity class tables: bit 31 = parity, low 31 bits = position of the
 // index within its class (natural order).
 constexpr uint32_t Z2_PAR = 0x80000000u;
+// dynamic LDS of one z2 tile workgroup: the hi and lo tiles
+inline size_t z2tile_lds_bytes(const ExpandParams &p) {
+    return (size_t)2 * p.tupb * p.L1 * p.tLD * sizeof(uint16_t);
+}
+constexpr size_t Z2TILE_MAX_LDS = 64 * 1024;
+constexpr int Z2TILE_MAX_THREADS = 512;
 
 // Generic contraction of two strided views (reverse pass):
 //   out[z(o)] (+)= alpha * sum_s X[x(o) + x(s)] * Y[y(o) + y(s)]

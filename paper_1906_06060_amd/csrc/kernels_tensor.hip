@@ -79,6 +79,16 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 __device__ __forceinline__ double bf16_value(uint16_t b) {
     return (double)__uint_as_float(((uint32_t)b) << 16);
 }
+// The same rounding (FP64 -> FP32 round-to-nearest-even, then FP32 -> bf16
+// round-to-nearest-even) on gfx950's conversion instruction.  The empty asm
+// keeps the compiler from fusing the two roundings into one FP64 -> bf16
+// rounding (which differs from the bit form above in rare double-rounding
+// cases).
+__device__ __forceinline__ uint16_t bf16_bits_hw(double a) {
+    float f = (float)a;
+    asm volatile("" : "+v"(f));
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
+}
 
 // row-major operand offset -> packed GEMM layout (identity when not packed)
 __device__ __forceinline__ size_t split_offset(const ExpandParams &p, uint32_t o) {
@@ -405,8 +415,161 @@ __global__ void __launch_bounds__(kThreads) iso_expand_z2run_kernel(ExpandParams
     }
 }
 
+// Tile form of the Z2 scatter (z2 == 3, bf16 hi / lo only; the layout of the
+// thread dims is described at ExpandParams).  Each tile is a rectangle of
+// natural rows [R0, R1) x natural K indices [K0, K1): in class order its
+// outputs form, per block, the class rows of one parity in a contiguous range
+// times the class-b K positions in a contiguous range.  The tile's threads
+// compute the allowed outputs with the arithmetic of iso_expand_z2run_kernel
+// and put them into an LDS copy of those two rectangles; the rectangles then
+// go out in the packed layout as 16-byte pieces (8 k of one row), lanes
+// ordered so that consecutive rows of one 32-k piece (consecutive 64-byte
+// runs) are written together.  Only the pieces at the two K ends of a
+// rectangle, shared with the neighbouring K groups, are written element by
+// element.
+//
+// Thread slots: a unit's inner threads are listed by the parity of their K
+// run (tperm, each parity padded to whole waves with idle slots ~0u), so in
+// every wave the test "K class of loop index l2 == block of row l1" has one
+// answer for all lanes and the skipped outputs cost no issue slots.  The
+// isometry block comes from tU, laid out [l1][l2][i], with wave-uniform
+// addresses (scalar loads), instead of a per-lane LDS copy.
+template <int N>
+__global__ void __launch_bounds__(Z2TILE_MAX_THREADS) iso_expand_z2tile_kernel(ExpandParams p,
+                                                                              const double *__restrict__ in,
+                                                                              const double *__restrict__ tU) {
+    extern __shared__ __align__(16) uint16_t sZt[];
+    uint16_t *th = sZt;
+    uint16_t *tl = th + (size_t)p.tupb * p.L1 * p.tLD;
+    const uint32_t LD = p.tLD;
+    const uint32_t per_group = (p.tNRP + p.tupb - 1) / p.tupb;
+    const uint32_t ntiles = p.tKg * per_group;
+    const uint32_t unit = threadIdx.x / p.tslots, slot = threadIdx.x - unit * p.tslots;
+    const uint32_t inner = p.tperm[slot];
+    // natural output offset and input offset of thread t of the launch
+    auto offsets = [&](uint32_t t, uint32_t &ib, uint32_t &ob) {
+        uint32_t rem = t;
+        ib = 0;
+        ob = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            const uint32_t q = fast_div(rem, p.ext[k]);
+            const uint32_t c = rem - q * p.ext[k].d;
+            ib += c * p.in_st[k];
+            ob += c * p.out_st[k];
+            rem = q;
+        }
+    };
+    // entries of class b before natural K index k (rows: of parity q before row r)
+    auto kcount = [&](uint32_t k, uint32_t b) -> uint32_t {
+        if (k >= p.zKc[0] + p.zKc[1]) return p.zKc[b];
+        const uint32_t kt = p.ktab[k], pos = kt & ~Z2_PAR;
+        return (kt >> 31) == b ? pos : k - pos;
+    };
+    auto rcount = [&](uint32_t r, uint32_t q) -> uint32_t {
+        if (r >= p.zM) return p.zNr[q];
+        const uint32_t rt = p.rtab[r], pos = rt & ~Z2_PAR;
+        return (rt >> 31) == q ? pos : r - pos;
+    };
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t kg = tile / per_group, u0 = (tile - kg * per_group) * p.tupb;
+        const uint32_t nu = min(p.tupb, p.tNRP - u0);
+        const uint32_t tfirst = (kg * p.tNRP + u0) * p.tP;
+        uint32_t ib0, ob0;
+        offsets(tfirst, ib0, ob0);
+        const uint32_t R0 = fast_div(ob0, p.zld), K0 = ob0 - R0 * p.zld.d;
+        const uint32_t R1 = R0 + nu * p.L1, K1 = K0 + p.tnK;
+        // per block b: class rows [rb0, rb0 + nr) of parity zP ^ zs ^ b (LDS
+        // rows from lr0), class K positions [ck, ck + nk) (LDS columns from the
+        // 8-aligned cal)
+        uint32_t nr[2], rb0[2], lr0[2], ck[2], nk[2], cal[2];
+#pragma unroll
+        for (uint32_t b = 0; b < 2; ++b) {
+            const uint32_t q = b ^ p.zP ^ p.zs;
+            rb0[b] = rcount(R0, q);
+            nr[b] = rcount(R1, q) - rb0[b];
+            ck[b] = kcount(K0, b);
+            nk[b] = kcount(K1, b) - ck[b];
+            cal[b] = ck[b] & ~7u;
+        }
+        lr0[0] = 0;
+        lr0[1] = nr[0];
+        if (unit < nu && inner != ~0u) {
+            uint32_t ib, ob;
+            offsets(tfirst + unit * p.tP + inner, ib, ob);
+            const uint32_t r0 = fast_div(ob, p.zld);
+            const uint32_t k0 = ob - r0 * p.zld.d;
+            uint32_t kt[N];
+#pragma unroll
+            for (int l2 = 0; l2 < N; ++l2) kt[l2] = p.ktab[k0 + l2 * p.o2];
+            double v[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = in[ib + i * p.xs];
+            for (int l1 = 0; l1 < p.L1; ++l1) {
+                const uint32_t rt = p.rtab[r0 + l1];
+                const uint32_t blk = (rt >> 31) ^ p.zP ^ p.zs;
+                // LDS index of class column col: lbase + col (col >= cal[blk])
+                const uint32_t lbase = (lr0[blk] + (rt & ~Z2_PAR) - rb0[blk]) * LD - cal[blk];
+                const double *ul = tU + (size_t)l1 * N * N;
+#pragma unroll
+                for (int l2 = 0; l2 < N; ++l2) {
+                    if ((kt[l2] >> 31) != blk) continue;  // structurally zero
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) acc = fma(ul[l2 * N + i], v[i], acc);
+                    const uint16_t h = bf16_bits_hw(acc);
+                    const uint32_t col = kt[l2] & ~Z2_PAR;
+                    th[lbase + col] = h;
+                    tl[lbase + col] = bf16_bits_hw(acc - bf16_value(h));
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t b = 0; b < 2; ++b) {
+            if (nr[b] == 0 || nk[b] == 0) continue;
+            const uint32_t g = b ^ p.zs;
+            const uint32_t prow0 = p.zrow_off[g] + rb0[b];
+            const uint32_t j0 = ck[b] >> 5, np = ((ck[b] + nk[b] - 1) >> 5) - j0 + 1;
+            const uint32_t items = np * nr[b] * 4, kend = ck[b] + nk[b];
+            uint16_t *__restrict__ ghi = p.zhi[b];
+            uint16_t *__restrict__ glo = p.zlo[b];
+            for (uint32_t w = threadIdx.x; w < items; w += blockDim.x) {
+                const uint32_t q = w & 3, rw = w >> 2;
+                const uint32_t jj = rw / nr[b], r = rw - jj * nr[b];
+                const uint32_t c0 = (j0 + jj) * 32 + q * 8;
+                if (c0 + 8 <= ck[b] || c0 >= kend) continue;
+                const uint32_t prow = prow0 + r;
+                const size_t go = ((size_t)(prow / PACK_ROWS) * p.zpkb[b] + (j0 + jj)) * (PACK_ROWS * PACK_K) +
+                                  (prow % PACK_ROWS) * PACK_K + q * 8;
+                const uint32_t lo_ = (lr0[b] + r) * LD + (c0 - cal[b]);
+                if (c0 >= ck[b] && c0 + 8 <= kend) {
+                    *(uint4 *)(ghi + go) = *(const uint4 *)(th + lo_);
+                    *(uint4 *)(glo + go) = *(const uint4 *)(tl + lo_);
+                } else {
+#pragma unroll
+                    for (uint32_t e = 0; e < 8; ++e)
+                        if (c0 + e >= ck[b] && c0 + e < kend) {
+                            ghi[go + e] = th[lo_ + e];
+                            glo[go + e] = tl[lo_ + e];
+                        }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int N>
 void launch_iso_expand_z2(const ExpandParams &p, bool split, const double *in, const double *U, hipStream_t s) {
+    if (p.z2 == 3) {
+        // the host checked the tile layout, split, the slot table, the thread
+        // count and the LDS size, and wrote tU
+        const uint32_t per_group = (p.tNRP + p.tupb - 1) / p.tupb;
+        const size_t tiles = (size_t)p.tKg * per_group;
+        const int g = (int)(tiles < 8192 ? tiles : 8192);
+        iso_expand_z2tile_kernel<N><<<g, (int)(p.tupb * p.tslots), z2tile_lds_bytes(p), s>>>(p, in, p.tU);
+        return;
+    }
     const size_t lds = (size_t)p.L1 * N * N * sizeof(double);
     const int g = grid_for(p.threads, kThreads, 4096);
     if (p.z2 == 2) {

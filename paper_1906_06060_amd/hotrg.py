@@ -330,6 +330,13 @@ class Context:
         _check(_lib.hotrg_kernel_stats(self._h, 0, C.byref(ms), C.byref(ln), C.byref(fl)))
         return dict(ms=ms.value, launches=ln.value, flops=fl.value)
 
+    def z2_tile_launches(self):
+        """Last isometry products since the last reset that wrote their bf16
+        Z2 operand blocks through LDS tiles (hotrg_kernel_stats kernel 4)."""
+        ln = C.c_longlong()
+        _check(_lib.hotrg_kernel_stats(self._h, 4, None, C.byref(ln), None))
+        return ln.value
+
     def phase_stats(self):
         """Device ms per phase of hotrg_step since the last reset (kernels 1..3),
         the GEMM ms (kernel 0) and the number of steps counted."""

@@ -155,3 +155,36 @@ def test_z2_flow_matches_oracle_dcut5(H):
         assert g["X"] == pytest.approx(r.X, rel=1e-8)
         assert g["m_imp"] == 0.0
     assert sum(g["block_sparse"] for g in got) == n - 1
+
+
+@pytest.mark.parametrize("budget", [0, 1])
+def test_z2_tile_scatter_bitwise_equals_element_scatter(H, monkeypatch, budget):
+    # The tile form of the last products' Z2 scatter (outputs gathered in LDS,
+    # written as whole 16-byte pieces) computes every operand entry with the
+    # same arithmetic in the same order as the element-wise scatter, and puts
+    # it at the same place: the bf16x3 flows must agree bit for bit, with and
+    # without K slices that fix b1'.
+    beta, dcut, n = 0.1497, 6, 8
+
+    def run():
+        out = []
+        with H.Context(beta, 0.0, dcut, precision=H.BF16X3, slice_budget=budget) as ctx:
+            for k in range(n):
+                ctx.step(k % 4)
+                out.append(ctx.observables())
+            tiles = ctx.z2_tile_launches()
+            tensors = [ctx.tensor(w) for w in range(3)]
+        return out, tiles, tensors
+
+    monkeypatch.setenv("HOTRG_Z2_TILE", "1")
+    a, ta, Ta = run()
+    monkeypatch.setenv("HOTRG_Z2_TILE", "0")
+    b, tb, Tb = run()
+    assert ta > 0 and tb == 0
+    for x, y in zip(a, b):
+        assert x["block_sparse"] == y["block_sparse"]
+        for key in ("lnz_per_site", "nn_imp", "X", "last_cn"):
+            assert x[key] == y[key], key
+        assert x["m_imp"] == 0.0 and y["m_imp"] == 0.0
+    for u, v in zip(Ta, Tb):
+        np.testing.assert_array_equal(u, v)
