@@ -117,9 +117,14 @@ struct hotrg_ctx {
     // class tables (z2_gen counts build_z2_tables calls)
     long long z2_gen = 0, tile_gen[2] = {-1, -1};
     std::vector<uint32_t> tperm_h[2];
+    std::vector<int32_t> tidx_h[2];  // compacted isometry block: source offsets (-1: zero)
     uint32_t *tperm_d[2] = {nullptr, nullptr};
+    int32_t *tidx_d[2] = {nullptr, nullptr};
     double *tU_d[2] = {nullptr, nullptr};
     uint32_t tslots[2] = {0, 0};
+    int tNH[2] = {0, 0};
+    uint32_t tlab1[2] = {0, 0}, tlab2[2] = {0, 0}, tnI[2][2] = {{0, 0}, {0, 0}};
+    uint64_t tI[2][2] = {{0, 0}, {0, 0}};
     double gemm_flops = 0;
     size_t device_bytes = 0;
     // phase timing of hotrg_step: events at the start, after the isometries,
@@ -656,9 +661,13 @@ int build_z2_tables(hotrg_ctx *c, int mu, const int tv[3], const int k[3], int E
 // class tables changed) and returns false, so that the run form is used,
 // when the layout does not match or a limit is exceeded.
 int z2_tile_plan(hotrg_ctx *c, ExpandParams &p, const double *U, uint64_t threads, int nko, int nro, uint64_t Ks,
-                 int id, bool *ok) {
+                 int id, const std::vector<uint8_t> *labs, bool *ok) {
     *ok = false;
-    if (id < 0 || id > 1 || nko < 0 || nro < 0 || nko + nro > p.nd || p.o1 != Ks) return HOTRG_OK;
+    if (id < 0 || id > 1 || nko < 0 || nro < 0 || nko + nro > p.nd || p.o1 != Ks || !labs) return HOTRG_OK;
+    // parity labels of the summed index, the first and the second loop index
+    if ((int)labs[0].size() != p.nsum || (int)labs[1].size() != p.L1 || (int)labs[2].size() != p.L2 ||
+        p.nsum > 13 || p.L1 > 13 || p.L2 > 13)
+        return HOTRG_OK;
     if (const char *e = getenv("HOTRG_Z2_TILE"))
         if (e[0] == '0') return HOTRG_OK;
     // inner dims and the second loop: a dense run [0, nK)
@@ -724,30 +733,52 @@ int z2_tile_plan(hotrg_ctx *c, ExpandParams &p, const double *U, uint64_t thread
         }
         if (tp.size() > (size_t)Z2TILE_MAX_THREADS) return HOTRG_OK;
         c->tslots[id] = (uint32_t)tp.size();
+        // summed indices by parity; the isometry block [l1][l2][j] over the
+        // j-th summed index of parity lab1(l1) ^ lab2(l2) (the others meet
+        // exact zeros of a one-sector column), NH entries, zero-padded
+        std::vector<int> I[2];
+        for (int i = 0; i < p.nsum; ++i) I[labs[0][i] & 1].push_back(i);
+        const int NH = z2tile_nh(p.nsum, (int)std::max(I[0].size(), I[1].size()));
+        for (int q = 0; q < 2; ++q) {
+            c->tnI[id][q] = (uint32_t)I[q].size();
+            c->tI[id][q] = 0;
+            for (size_t j = 0; j < I[q].size(); ++j) c->tI[id][q] |= (uint64_t)I[q][j] << (4 * j);
+        }
+        c->tlab1[id] = c->tlab2[id] = 0;
+        for (int l = 0; l < p.L1; ++l) c->tlab1[id] |= (uint32_t)(labs[1][l] & 1) << l;
+        for (int l = 0; l < p.L2; ++l) c->tlab2[id] |= (uint32_t)(labs[2][l] & 1) << l;
+        c->tNH[id] = NH;
+        auto &ti = c->tidx_h[id];
+        ti.assign((size_t)p.L1 * p.L2 * NH, -1);
+        for (int l1 = 0; l1 < p.L1; ++l1)
+            for (int l2 = 0; l2 < p.L2; ++l2) {
+                const int need = (labs[1][l1] ^ labs[2][l2]) & 1;
+                for (size_t j = 0; j < I[need].size() && (int)j < NH; ++j)
+                    ti[((size_t)l1 * p.L2 + l2) * NH + j] =
+                        (int32_t)((uint64_t)l1 * p.u1 + (uint64_t)l2 * p.u2 + (uint64_t)I[need][j] * p.us);
+            }
         if (!c->tperm_d[id]) TRY(alloc_n(c, &c->tperm_d[id], (size_t)Z2TILE_MAX_THREADS));
+        if (!c->tidx_d[id]) TRY(alloc_n(c, &c->tidx_d[id], (size_t)13 * 13 * 13));
         if (!c->tU_d[id]) TRY(alloc_n(c, &c->tU_d[id], (size_t)13 * 13 * 13));
         HIP_TRY(c, hipMemcpyAsync(c->tperm_d[id], tp.data(), sizeof(uint32_t) * tp.size(), hipMemcpyHostToDevice,
                                   c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->tidx_d[id], ti.data(), sizeof(int32_t) * ti.size(), hipMemcpyHostToDevice,
+                                  c->stream));
         c->tile_gen[id] = c->z2_gen;
     }
-    // the isometry block in use order [l1][l2][i] (a tiny gather, every call:
-    // the two A / B products of a step share it, S_m / S_e reuse it)
-    if ((uint64_t)p.L1 * p.L2 * p.nsum > 13 * 13 * 13) return HOTRG_OK;
-    {
-        PermParams pp{};
-        pp.nd = 3;
-        const uint32_t e3[3] = {(uint32_t)p.L1, (uint32_t)p.L2, (uint32_t)p.nsum};
-        const uint32_t s3[3] = {p.u1, p.u2, p.us};
-        for (int k = 0; k < 3; ++k) {
-            pp.ext[k] = make_fastdiv(e3[k]);
-            pp.in_st[k] = s3[k];
-        }
-        pp.total = e3[0] * e3[1] * e3[2];
-        launch_permute(pp, U, c->tU_d[id], 1.0, c->stream);
-    }
+    // the compacted isometry block (a tiny gather, every call: the A products
+    // of T, S_m, S_e share the isometry, but it is cheap)
+    launch_gather_or_zero(U, c->tidx_d[id], c->tU_d[id], (int)c->tidx_h[id].size(), c->stream);
     p.tslots = c->tslots[id];
     p.tperm = c->tperm_d[id];
     p.tU = c->tU_d[id];
+    p.tNH = c->tNH[id];
+    p.tlab1 = c->tlab1[id];
+    p.tlab2 = c->tlab2[id];
+    for (int q = 0; q < 2; ++q) {
+        p.tI[q] = c->tI[id][q];
+        p.tnI[q] = c->tnI[id][q];
+    }
     p.tLD = (uint32_t)((maxnk + 7 + 7) / 8 * 8);
     p.tP = (uint32_t)P;
     p.tNRP = (uint32_t)NRP;
@@ -769,7 +800,7 @@ int z2_tile_plan(hotrg_ctx *c, ExpandParams &p, const double *U, uint64_t thread
 // tile form is used.
 int z2_scatter(hotrg_ctx *c, XP &x, const double *U, uint64_t Ks, uint32_t zs, uint32_t zP, const uint32_t off[2],
                uint64_t rows_cap, bool mixed, double *const out[2], uint16_t *const hi[2], uint16_t *const lo[2],
-               int nko = -1, int nro = -1, int tile_id = -1) {
+               int nko = -1, int nro = -1, int tile_id = -1, const std::vector<uint8_t> *labs = nullptr) {
     ExpandParams &p = x.p;
     const auto &zl = c->z2l;
     if (p.nsum != p.L2 || p.L2 > 13 || (size_t)p.L1 * p.L2 * p.L2 * sizeof(double) > 48 * 1024)
@@ -804,7 +835,7 @@ int z2_scatter(hotrg_ctx *c, XP &x, const double *U, uint64_t Ks, uint32_t zs, u
     }
     if (mixed && p.z2 == 2 && (((uintptr_t)hi[0] | (uintptr_t)hi[1] | (uintptr_t)lo[0] | (uintptr_t)lo[1]) & 15) == 0) {
         bool ok = false;
-        TRY(z2_tile_plan(c, p, U, x.threads, nko, nro, Ks, tile_id, &ok));
+        TRY(z2_tile_plan(c, p, U, x.threads, nko, nro, Ks, tile_id, labs, &ok));
         if (ok) {
             p.z2 = 3;
             c->z2_tile_launches++;
@@ -978,6 +1009,9 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
     const uint64_t ldn = z2 ? Ks : ld;
     const uint64_t rs0 = (uint64_t)kb * Dm * kc * ldn, rs1 = (uint64_t)Dm * kc * ldn, rs2 = (uint64_t)kc * ldn;
     bool z2_init[2] = {false, false};
+    // labels of the last products' summed index, first and second loop index:
+    // old c, new c, old c (both products)
+    const std::vector<uint8_t> tile_labs[3] = {c->par[tv[2]], c->new_par[tv[2]], c->par[tv[2]]};
 
     bool first_slice = true;
     const int nslices = Dm * Da * (Db / Eb);
@@ -1045,7 +1079,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                         for (int gg = 0; gg < 2; ++gg)
                             off[gg] = t == 0 ? 0u : (t == 1 ? zl.N[gg] : (uint32_t)M);
                         TRY(z2_scatter(c, x, Uc, Ks, zs, t == 1 ? 1u : 0u, off, z2_arows, mixed, zA, zAh, zAl, 2, 3,
-                                       0));
+                                       0, tile_labs));
                         launch_iso_expand(x.done(), c->y2, Uc, nullptr, nullptr, nullptr, c->stream);
                     } else if (mixed && stack) {  // rows t*M .. t*M + M - 1 of one packed block
                         x.packed(ld, (uint32_t)(t * M));
@@ -1112,7 +1146,7 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     if (!x.fits(c->cap, usz[2], M * ldn)) return set_err(HOTRG_EINVAL, "Q3 launch out of bounds");
                     if (z2) {
                         const uint32_t off[2] = {0u, 0u};
-                        TRY(z2_scatter(c, x, Uc, Ks, zs, 0u, off, z2_brows, mixed, zB, zBh, zBl, 2, 3, 1));
+                        TRY(z2_scatter(c, x, Uc, Ks, zs, 0u, off, z2_brows, mixed, zB, zBh, zBl, 2, 3, 1, tile_labs));
                         launch_iso_expand(x.done(), c->y2, Uc, nullptr, nullptr, nullptr, c->stream);
                     } else if (mixed) {
                         x.packed(ld);

@@ -86,7 +86,11 @@ struct ExpandParams {
     uint32_t tLD;     // LDS row length of a tile (bf16 elements, multiple of 8)
     uint32_t tslots;  // thread slots per unit (a multiple of 64)
     const uint32_t *tperm;  // slot -> inner thread (~0u: idle), K-run parity 0 first
-    const double *tU;       // the isometry block as [l1][l2][i] (L1 x L2 x nsum)
+    const double *tU;       // the isometry block as [l1][l2][j], j < tNH (see the kernel)
+    int tNH;                // compacted summed-index count (z2tile_nh)
+    uint32_t tlab1, tlab2;  // parity labels of the loop indices l1, l2 (bit l = label of index l)
+    uint64_t tI[2];         // summed indices of parity 0 / 1, 4 bits each in order
+    uint32_t tnI[2];        // their counts
     uint32_t zKc[2];  // K indices of each class (size of ktab = zKc[0] + zKc[1])
     uint32_t zNr[2];  // rows of each parity (size of rtab = zM)
     uint32_t zM;
@@ -151,6 +155,11 @@ struct PermParams {
 void launch_init_site(double *T, double *S, double w00, double w01, double w10, double w11,
                       double v_up, double v_dn, hipStream_t s);
 void launch_permute(const PermParams &p, const double *in, double *out, double scale, hipStream_t s);
+// dst[j] = src[idx[j]], or 0 where idx[j] < 0, for j < n
+void launch_gather_or_zero(const double *src, const int32_t *idx, double *dst, int n, hipStream_t s);
+// compacted summed-index count the z2 tile kernel is compiled for, given the
+// larger parity class nmax of an N-value summed index (N when no split fits)
+int z2tile_nh(int N, int nmax);
 // out (FP64) or hi/lo (bf16 split) when hi != nullptr
 void launch_iso_expand(const ExpandParams &p, const double *in, const double *U, double *out,
                        uint16_t *hi, uint16_t *lo, hipStream_t s);

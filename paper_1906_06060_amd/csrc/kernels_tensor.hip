@@ -431,10 +431,22 @@ __global__ void __launch_bounds__(kThreads) iso_expand_z2run_kernel(ExpandParams
 // Thread slots: a unit's inner threads are listed by the parity of their K
 // run (tperm, each parity padded to whole waves with idle slots ~0u), so in
 // every wave the test "K class of loop index l2 == block of row l1" has one
-// answer for all lanes and the skipped outputs cost no issue slots.  The
-// isometry block comes from tU, laid out [l1][l2][i], with wave-uniform
-// addresses (scalar loads), instead of a per-lane LDS copy.
-template <int N>
+// answer for all lanes and the skipped outputs cost no issue slots.
+//
+// Isometry zeros: a column of the isometry lies in one parity sector, so for
+// an output (l1, l2) only the summed indices i of parity need(l1, l2) =
+// lab1(l1) ^ lab2(l2) contribute (the others meet exact zeros).  For the
+// outputs a wave computes at one l1 that parity is the same for every lane.
+// The input run is loaded twice, compacted to the indices of parity 0 (v0)
+// and of parity 1 (v1), NH values each (zero-padded), and tU holds the
+// isometry block as [l1][l2][j], j < NH, with entry j the j-th index of
+// parity need(l1, l2) (zero past the count): NH FMAs per output instead of N,
+// in the same order over the contributing indices (the dropped terms are
+// exact zeros).  tU is read with wave-uniform addresses (scalar loads).
+//
+// The next tile's input runs and K table entries are loaded before the
+// current tile's LDS rectangles are written out.
+template <int N, int NH>
 __global__ void __launch_bounds__(Z2TILE_MAX_THREADS) iso_expand_z2tile_kernel(ExpandParams p,
                                                                               const double *__restrict__ in,
                                                                               const double *__restrict__ tU) {
@@ -470,12 +482,34 @@ __global__ void __launch_bounds__(Z2TILE_MAX_THREADS) iso_expand_z2tile_kernel(E
         const uint32_t rt = p.rtab[r], pos = rt & ~Z2_PAR;
         return (rt >> 31) == q ? pos : r - pos;
     };
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // this thread's work in a tile: input runs and K table entries
+    double v0[NH], v1[NH];
+    uint32_t kt[N];
+    uint32_t r0 = 0;
+    auto fetch = [&](uint32_t tl_) -> bool {
+        const uint32_t kg = tl_ / per_group, u0 = (tl_ - kg * per_group) * p.tupb;
+        if (unit >= min(p.tupb, p.tNRP - u0) || inner == ~0u) return false;
+        uint32_t ib, ob;
+        offsets((kg * p.tNRP + u0) * p.tP + unit * p.tP + inner, ib, ob);
+        r0 = fast_div(ob, p.zld);
+        const uint32_t k0 = ob - r0 * p.zld.d;
+#pragma unroll
+        for (int l2 = 0; l2 < N; ++l2) kt[l2] = p.ktab[k0 + l2 * p.o2];
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+            const uint32_t i0 = (uint32_t)(p.tI[0] >> (4 * j)) & 15u, i1 = (uint32_t)(p.tI[1] >> (4 * j)) & 15u;
+            v0[j] = j < (int)p.tnI[0] ? in[ib + i0 * p.xs] : 0.0;
+            v1[j] = j < (int)p.tnI[1] ? in[ib + i1 * p.xs] : 0.0;
+        }
+        return true;
+    };
+    uint32_t tile = blockIdx.x;
+    bool active = tile < ntiles && fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
         const uint32_t kg = tile / per_group, u0 = (tile - kg * per_group) * p.tupb;
         const uint32_t nu = min(p.tupb, p.tNRP - u0);
-        const uint32_t tfirst = (kg * p.tNRP + u0) * p.tP;
         uint32_t ib0, ob0;
-        offsets(tfirst, ib0, ob0);
+        offsets((kg * p.tNRP + u0) * p.tP, ib0, ob0);
         const uint32_t R0 = fast_div(ob0, p.zld), K0 = ob0 - R0 * p.zld.d;
         const uint32_t R1 = R0 + nu * p.L1, K1 = K0 + p.tnK;
         // per block b: class rows [rb0, rb0 + nr) of parity zP ^ zs ^ b (LDS
@@ -493,42 +527,45 @@ __global__ void __launch_bounds__(Z2TILE_MAX_THREADS) iso_expand_z2tile_kernel(E
         }
         lr0[0] = 0;
         lr0[1] = nr[0];
-        if (unit < nu && inner != ~0u) {
-            uint32_t ib, ob;
-            offsets(tfirst + unit * p.tP + inner, ib, ob);
-            const uint32_t r0 = fast_div(ob, p.zld);
-            const uint32_t k0 = ob - r0 * p.zld.d;
-            uint32_t kt[N];
-#pragma unroll
-            for (int l2 = 0; l2 < N; ++l2) kt[l2] = p.ktab[k0 + l2 * p.o2];
-            double v[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = in[ib + i * p.xs];
+        if (active) {
+            // class of loop index l2 = Q ^ lab2(l2)
+            const uint32_t Q = (kt[0] >> 31) ^ (p.tlab2 & 1u);
             for (int l1 = 0; l1 < p.L1; ++l1) {
                 const uint32_t rt = p.rtab[r0 + l1];
                 const uint32_t blk = (rt >> 31) ^ p.zP ^ p.zs;
                 // LDS index of class column col: lbase + col (col >= cal[blk])
                 const uint32_t lbase = (lr0[blk] + (rt & ~Z2_PAR) - rb0[blk]) * LD - cal[blk];
-                const double *ul = tU + (size_t)l1 * N * N;
+                const double *ul = tU + (size_t)l1 * N * NH;
+                auto row = [&](const double (&w)[NH]) {
 #pragma unroll
-                for (int l2 = 0; l2 < N; ++l2) {
-                    if ((kt[l2] >> 31) != blk) continue;  // structurally zero
-                    double acc = 0.0;
+                    for (int l2 = 0; l2 < N; ++l2) {
+                        if ((kt[l2] >> 31) != blk) continue;  // structurally zero
+                        double acc = 0.0;
 #pragma unroll
-                    for (int i = 0; i < N; ++i) acc = fma(ul[l2 * N + i], v[i], acc);
-                    const uint16_t h = bf16_bits_hw(acc);
-                    const uint32_t col = kt[l2] & ~Z2_PAR;
-                    th[lbase + col] = h;
-                    tl[lbase + col] = bf16_bits_hw(acc - bf16_value(h));
-                }
+                        for (int j = 0; j < NH; ++j) acc = fma(ul[l2 * NH + j], w[j], acc);
+                        const uint16_t h = bf16_bits_hw(acc);
+                        const uint32_t col = kt[l2] & ~Z2_PAR;
+                        th[lbase + col] = h;
+                        tl[lbase + col] = bf16_bits_hw(acc - bf16_value(h));
+                    }
+                };
+                // parity of the contributing summed indices (the allowed l2 have lab2 = Q ^ blk)
+                if ((((p.tlab1 >> l1) & 1u) ^ Q ^ blk) != 0u)
+                    row(v1);
+                else
+                    row(v0);
             }
         }
+        // the next tile's loads go out before this tile's rectangles
+        const uint32_t next = tile + gridDim.x;
+        const uint32_t rb0c[2] = {rb0[0], rb0[1]};
+        active = next < ntiles && fetch(next);
         __syncthreads();
 #pragma unroll
         for (uint32_t b = 0; b < 2; ++b) {
             if (nr[b] == 0 || nk[b] == 0) continue;
             const uint32_t g = b ^ p.zs;
-            const uint32_t prow0 = p.zrow_off[g] + rb0[b];
+            const uint32_t prow0 = p.zrow_off[g] + rb0c[b];
             const uint32_t j0 = ck[b] >> 5, np = ((ck[b] + nk[b] - 1) >> 5) - j0 + 1;
             const uint32_t items = np * nr[b] * 4, kend = ck[b] + nk[b];
             uint16_t *__restrict__ ghi = p.zhi[b];
@@ -559,15 +596,46 @@ __global__ void __launch_bounds__(Z2TILE_MAX_THREADS) iso_expand_z2tile_kernel(E
     }
 }
 
+// tU[j] = src[idx[j]] (0 where idx[j] < 0)
+__global__ void gather_or_zero_kernel(const double *__restrict__ src, const int32_t *__restrict__ idx,
+                                      double *__restrict__ dst, int n) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) dst[j] = idx[j] >= 0 ? src[idx[j]] : 0.0;
+}
+void launch_gather_or_zero(const double *src, const int32_t *idx, double *dst, int n, hipStream_t s) {
+    if (n > 0) gather_or_zero_kernel<<<(n + 255) / 256, 256, 0, s>>>(src, idx, dst, n);
+}
+
+template <int N, int NH>
+void launch_z2tile(const ExpandParams &p, const double *in, hipStream_t s) {
+    const uint32_t per_group = (p.tNRP + p.tupb - 1) / p.tupb;
+    const size_t tiles = (size_t)p.tKg * per_group;
+    const int g = (int)(tiles < 8192 ? tiles : 8192);
+    iso_expand_z2tile_kernel<N, NH><<<g, (int)(p.tupb * p.tslots), z2tile_lds_bytes(p), s>>>(p, in, p.tU);
+}
+
+// NH = N always; for N >= 8 also the two near-even splits
+template <int N>
+void launch_z2tile_nh(const ExpandParams &p, const double *in, hipStream_t s) {
+    constexpr int H = (N + 1) / 2;
+    if constexpr (N >= 8) {
+        if (p.tNH == H) return launch_z2tile<N, H>(p, in, s);
+        if (p.tNH == H + 1) return launch_z2tile<N, H + 1>(p, in, s);
+    }
+    launch_z2tile<N, N>(p, in, s);
+}
+
+int z2tile_nh(int N, int nmax) {
+    const int H = (N + 1) / 2;
+    return N >= 8 && nmax <= H ? H : (N >= 8 && nmax == H + 1 ? H + 1 : N);
+}
+
 template <int N>
 void launch_iso_expand_z2(const ExpandParams &p, bool split, const double *in, const double *U, hipStream_t s) {
     if (p.z2 == 3) {
         // the host checked the tile layout, split, the slot table, the thread
         // count and the LDS size, and wrote tU
-        const uint32_t per_group = (p.tNRP + p.tupb - 1) / p.tupb;
-        const size_t tiles = (size_t)p.tKg * per_group;
-        const int g = (int)(tiles < 8192 ? tiles : 8192);
-        iso_expand_z2tile_kernel<N><<<g, (int)(p.tupb * p.tslots), z2tile_lds_bytes(p), s>>>(p, in, p.tU);
+        launch_z2tile_nh<N>(p, in, s);
         return;
     }
     const size_t lds = (size_t)p.L1 * N * N * sizeof(double);
