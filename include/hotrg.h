@@ -241,7 +241,9 @@ int hotrg_get_spectrum(hotrg_ctx *ctx, int q, int side, double *out, size_t coun
  * steps wrote their bf16 operand blocks through LDS tiles in whole 16-byte
  * pieces (the rest scatter element by element; the environment variable
  * HOTRG_Z2_TILE=0 selects that for every launch; both give identical bits);
- * ms = flops = 0. */
+ * ms = flops = 0.
+ * kernel 5: launches = steps that hotrg_backward undid in the Z2 block form
+ * (those whose forward contraction ran in it); ms = flops = 0. */
 int hotrg_kernel_stats(hotrg_ctx *ctx, int kernel, double *ms, long long *launches, double *flops);
 int hotrg_reset_stats(hotrg_ctx *ctx);
 

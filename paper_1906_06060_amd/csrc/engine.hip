@@ -112,6 +112,7 @@ struct hotrg_ctx {
     double gemm_ms = 0;
     long long gemm_launches = 0;
     long long z2_tile_launches = 0;  // last isometry products run in the tile form of the Z2 scatter
+    long long z2_rev_steps = 0;      // reverse-pass steps undone in the Z2 block form
     // tile form of the Z2 scatter, per last product (0: A rows, 1: B rows):
     // the slot table and the permuted isometry block, rebuilt once per set of
     // class tables (z2_gen counts build_z2_tables calls)
@@ -164,6 +165,9 @@ struct hotrg_ctx {
         bool trunc[3];    // isometry from an eigendecomposition (else constant)
         bool flagged[3];  // the cut stayed inside a degenerate multiplet (no gap above tau)
         double c;         // c_n of the step
+        bool z2 = false;  // the step contracted in the Z2 block form (its labels below)
+        std::vector<uint8_t> par[4];   // parity labels of the bonds before the step
+        std::vector<uint8_t> npar[3];  // labels of the new transverse bonds (axis tv[i])
         double *T;        // state before the step
         double *U[3];     // n x k
         double *lam[3];   // n (chosen side, descending)
@@ -174,7 +178,8 @@ struct hotrg_ctx {
     bool ckpt_broken = false;
     double c0 = 1.0;
     // reverse-pass work buffers
-    DevBuf bw[14];
+    DevBuf bw[18];
+    uint32_t *rev_tabs = nullptr;  // reverse pass, block form: class lists and Tbar offsets of the rows
 };
 
 namespace {
@@ -1342,6 +1347,11 @@ int save_checkpoint_into(hotrg_ctx *c, hotrg_ctx::Checkpoint &cp, int axis, cons
                          bool given_u) {
     for (int q = 0; q < 4; ++q) cp.dims[q] = c->dims[q];
     cp.axis = axis;
+    cp.z2 = c->step_z2;
+    if (cp.z2) {
+        for (int q = 0; q < 4; ++q) cp.par[q] = c->par[q];
+        for (int i = 0; i < 3; ++i) cp.npar[i] = c->new_par[tv[i]];
+    }
     const size_t ts = tensor_size(c->dims);
     TRY(alloc_n(c, &cp.T, ts));
     HIP_TRY(c, hipMemcpyAsync(cp.T, c->state[0], sizeof(double) * ts, hipMemcpyDeviceToDevice, c->stream));
@@ -1555,7 +1565,10 @@ int read_obs(hotrg_ctx *c, double *tr, double *trm, double *tre, std::vector<dou
 enum {
     BW_TBAR0, BW_TBAR1, BW_CBAR, BW_CBART, BW_AT, BW_BT, BW_ABAR, BW_BBAR, BW_Z1, BW_Z2, BW_YB1, BW_YB2,
     BW_X3,   // packed bf16 hi / lo of C_bar, C_bar^T, A^T, B^T (mixed precision)
-    BW_PART  // per-workgroup isometry-adjoint sums of the fused last-product adjoint
+    BW_PART, // per-workgroup isometry-adjoint sums of the fused last-product adjoint
+    BW_ZC,   // block form: packed bf16 hi / lo of the C_bar class blocks and their transposes
+    BW_ZT,   // block form: transposed class operands A_b^T, B_b^T (FP64 or packed bf16 hi / lo)
+    BW_ZO    // block form: class-block GEMM outputs A_bar_b, B_bar_b
 };
 
 template <typename T>
@@ -1592,6 +1605,118 @@ int run_lastprod(hotrg_ctx *c, const LastProdParams &p, const double *X, uint64_
     if (!launch_lastprod_adjoint(p, X, Y, U, out, Ubar, part, c->stream)) return HOTRG_OK;
     *done = true;
     return check_launch(c, "last-product adjoint");
+}
+
+// Class tables of a checkpointed block-form step for its reverse pass (pure
+// T): rows (a, b, mu1, c) with the new transverse labels and the mu labels,
+// inner K indices of a slice in the dense order (b1', c1', a2, b2, c2) with
+// the old labels (b1' in the slice parity when a slice fixes it); the rows of
+// each class in class order (inv), and every row's and column's offset in
+// Tbar (st: strides of (a, b, mu1, c) and (a', b', mu2', c') in Tbar).  The
+// device tables c->rtab / c->ktab are overwritten (the next forward step
+// rebuilds them).
+int build_rev_z2(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, int Eb, const uint32_t st[8], uint32_t N[2],
+                 uint32_t Kc[2], uint32_t **inv, uint32_t **roff, uint32_t **coff) {
+    const int *D = cp.dims;
+    const int *tv = cp.tv, mu = cp.axis;
+    const int Da = D[tv[0]], Db = D[tv[1]], Dc = D[tv[2]], Dm = D[mu];
+    const int ka = cp.k[0], kb = cp.k[1], kc = cp.k[2];
+    const auto &pa = cp.npar[0], &pb = cp.npar[1], &pc = cp.npar[2], &pm = cp.par[mu];
+    const auto &oa = cp.par[tv[0]], &ob = cp.par[tv[1]], &oc = cp.par[tv[2]];
+    if ((int)pa.size() != ka || (int)pb.size() != kb || (int)pc.size() != kc || (int)pm.size() != Dm ||
+        (int)oa.size() != Da || (int)ob.size() != Db || (int)oc.size() != Dc)
+        return set_err(HOTRG_EINVAL, "reverse pass: checkpoint Z2 labels do not match the bond dimensions");
+    const uint32_t M = (uint32_t)ka * kb * Dm * kc;
+    auto &rt = c->rtab_h;
+    rt.resize(M);
+    std::vector<uint32_t> hv((size_t)3 * M);  // inv | roff | coff
+    uint32_t cnt[2] = {0, 0}, r = 0;
+    std::vector<uint32_t> lists[2];
+    for (int a = 0; a < ka; ++a)
+        for (int b = 0; b < kb; ++b)
+            for (int m = 0; m < Dm; ++m)
+                for (int cc = 0; cc < kc; ++cc) {
+                    const int p = pa[a] ^ pb[b] ^ pm[m] ^ pc[cc];
+                    rt[r] = (p ? Z2_PAR : 0u) | cnt[p]++;
+                    lists[p].push_back(r);
+                    hv[M + r] = a * st[0] + b * st[1] + m * st[2] + cc * st[3];
+                    hv[2 * (size_t)M + r] = a * st[4] + b * st[5] + m * st[6] + cc * st[7];
+                    ++r;
+                }
+    std::copy(lists[0].begin(), lists[0].end(), hv.begin());
+    std::copy(lists[1].begin(), lists[1].end(), hv.begin() + lists[0].size());
+    const uint32_t Ks = (uint32_t)Eb * Dc * Da * Db * Dc;
+    auto &kt = c->ktab_h;
+    kt.resize(Ks);
+    uint32_t kcnt[2] = {0, 0}, kk = 0;
+    for (int b1 = 0; b1 < Eb; ++b1)
+        for (int c1 = 0; c1 < Dc; ++c1)
+            for (int a2 = 0; a2 < Da; ++a2)
+                for (int b2 = 0; b2 < Db; ++b2)
+                    for (int c2 = 0; c2 < Dc; ++c2) {
+                        const int p = (Eb == Db ? ob[b1] : 0) ^ oc[c1] ^ oa[a2] ^ ob[b2] ^ oc[c2];
+                        kt[kk++] = (p ? Z2_PAR : 0u) | kcnt[p]++;
+                    }
+    for (int g = 0; g < 2; ++g) {
+        N[g] = cnt[g];
+        Kc[g] = kcnt[g];
+    }
+    const size_t Dmax = (size_t)std::max(c->dcut, 2);
+    if (!c->rtab) TRY(alloc_n(c, &c->rtab, Dmax * Dmax * Dmax * Dmax));
+    if (!c->ktab) TRY(alloc_n(c, &c->ktab, Dmax * Dmax * Dmax * Dmax * Dmax));
+    if (!c->rev_tabs) TRY(alloc_n(c, &c->rev_tabs, 3 * Dmax * Dmax * Dmax * Dmax));
+    HIP_TRY(c, hipMemcpyAsync(c->rtab, rt.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->ktab, kt.data(), sizeof(uint32_t) * Ks, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->rev_tabs, hv.data(), sizeof(uint32_t) * hv.size(), hipMemcpyHostToDevice,
+                              c->stream));
+    // the host vectors must outlive the copies
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->z2_gen++;
+    *inv = c->rev_tabs;
+    *roff = c->rev_tabs + M;
+    *coff = c->rev_tabs + 2 * (size_t)M;
+    return HOTRG_OK;
+}
+
+// Transposed block scatter of a reverse-pass operand product (natural offset
+// o = K M + r): checks that the thread dims split into K digits (strides
+// multiples of M) and row digits (strides below M) without carries, and sets
+// the block outputs (block b: rows K_b, row length ld[b ^ zs]).
+int z2t_scatter(hotrg_ctx *c, XP &x, uint64_t M, uint64_t Ks, uint32_t zs, const uint32_t N[2], const uint32_t Kc[2],
+                const uint64_t ld[2], bool mixed, double *const out[2], uint16_t *const hi[2],
+                uint16_t *const lo[2]) {
+    ExpandParams &p = x.p;
+    if (p.nsum != p.L2 || p.L2 > 13 || (size_t)p.L1 * p.L2 * p.L2 * sizeof(double) > 48 * 1024)
+        return set_err(HOTRG_EINVAL, "reverse Z2 scatter: unsupported product shape");
+    if (p.o1 >= M || p.o2 % M != 0) return set_err(HOTRG_EINVAL, "reverse Z2 scatter: unsupported loop strides");
+    uint64_t rmax = (uint64_t)(p.L1 - 1) * p.o1, kmax = (uint64_t)(p.L2 - 1) * (p.o2 / M);
+    for (int d = 0; d < p.nd; ++d) {
+        const uint64_t stv = p.out_st[d], ext = p.ext[d].d;
+        if (stv % M == 0) kmax += (ext - 1) * (stv / M);
+        else if (stv < M) rmax += (ext - 1) * stv;
+        else return set_err(HOTRG_EINVAL, "reverse Z2 scatter: a thread dim mixes rows and K");
+    }
+    if (rmax >= M || kmax >= Ks) return set_err(HOTRG_EINVAL, "reverse Z2 scatter: launch out of bounds");
+    for (int b = 0; b < 2; ++b)
+        if (ld[b ^ zs] < N[b ^ zs]) return set_err(HOTRG_EINVAL, "reverse Z2 scatter: block row too short");
+    (void)Kc;
+    p.z2 = 4;
+    p.zrs = (uint32_t)(p.o2 / M);
+    p.zld = make_fastdiv((uint32_t)M);
+    p.rtab = c->rtab;
+    p.ktab = c->ktab;
+    p.zs = zs;
+    p.zP = 0;
+    for (int b = 0; b < 2; ++b) {
+        const uint32_t g = (uint32_t)b ^ zs;
+        p.zrow_off[b] = 0;
+        p.zld_out[b] = (uint32_t)ld[g];
+        p.zpkb[b] = (uint32_t)(ld[g] / PACK_K);
+        p.zout[b] = mixed ? nullptr : out[b];
+        p.zhi[b] = mixed ? hi[b] : nullptr;
+        p.zlo[b] = mixed ? lo[b] : nullptr;
+    }
+    return HOTRG_OK;
 }
 
 // Tbar_prev (dims of the checkpoint) = adjoint of one step applied to Tbar
@@ -1634,17 +1759,32 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
     if (M * Ks >= (1ull << 31) || M * M >= (1ull << 31))
         return set_err(HOTRG_ENOMEM, "reverse pass: operand slice exceeds 2^31 elements");
 
+    // Z2 block form (the forward step ran in it): the reverse GEMMs split per
+    // parity class like the forward's, A_bar_b = C_bar_g B_b, B_bar_b =
+    // C_bar_g^T A_b (g = b ^ slice parity), on class blocks built from the
+    // checkpoint's labels; their outputs go back to the natural layout (exact
+    // zeros elsewhere) for the adjoint contractions below
+    const bool z2 = cp.z2;
+    uint32_t zN[2] = {0, 0}, zKc[2] = {0, 0};  // rows (= columns) and inner K indices per class
+    uint64_t zld[2] = {0, 0};                  // k-dim row length of class g's operands
+    uint16_t *zCh[2] = {}, *zCl[2] = {}, *zCTh[2] = {}, *zCTl[2] = {};
+    uint16_t *zATh[2] = {}, *zATl[2] = {}, *zBTh[2] = {}, *zBTl[2] = {};
+    double *zAT[2] = {}, *zBT[2] = {}, *zAo[2] = {}, *zBo[2] = {};
     double *Cbar, *CbarT, *AT = nullptr, *BT = nullptr, *Abar, *Bbar, *Z1, *Z2, *Yb1, *Yb2;
     TRY(bw_buf(c, BW_CBAR, M * M, &Cbar));
     TRY(bw_buf(c, BW_CBART, M * M, &CbarT));
     // mixed precision: the reverse GEMMs run as bf16x3 products on packed
     // operands with row length ldM (the recomputed A^T, B^T go there directly)
-    const uint64_t ldM = mixed ? (M + 63) / 64 * 64 : M;  // row length of A^T, B^T (and C_bar splits)
+    // (block form: the transposed operands' natural offsets K M + r are split by the scatter)
+    const uint64_t ldM = mixed && !z2 ? (M + 63) / 64 * 64 : M;  // row length of A^T, B^T (and C_bar splits)
     const uint64_t pC = packed_rows(M) * ldM, pK = packed_rows(Ks) * ldM;
     uint16_t *Ch = nullptr, *Cl = nullptr, *CTh = nullptr, *CTl = nullptr;
     uint16_t *ATh = nullptr, *ATl = nullptr, *BTh = nullptr, *BTl = nullptr;
     double *tail = nullptr;
-    if (mixed) {
+    if (mixed && z2) {
+        TRY(ensure(c, c->gemm_tail, sizeof(double) * GEMM_TAIL_MAX_TILES * 256 * 256));
+        tail = (double *)c->gemm_tail.p;
+    } else if (mixed) {
         if (M * ldM >= (1ull << 32) || Ks * ldM >= (1ull << 31))
             return set_err(HOTRG_ENOMEM, "reverse pass: packed operand exceeds 2^31 elements");
         TRY(ensure(c, c->gemm_tail, sizeof(double) * GEMM_TAIL_MAX_TILES * 256 * 256));
@@ -1661,7 +1801,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
         BTl = BTh + pK;
         // padding columns of A^T, B^T are never written by the products
         if (ldM != M) HIP_TRY(c, hipMemsetAsync(ATh, 0, sizeof(uint16_t) * 4 * pK, c->stream));
-    } else {
+    } else if (!z2) {
         TRY(bw_buf(c, BW_AT, M * Ks, &AT));
         TRY(bw_buf(c, BW_BT, M * Ks, &BT));
     }
@@ -1691,6 +1831,90 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
         uint64_t mx;
         PermParams pp = perm_params(8, ext, st, &mx);
         if (mx >= M * M) return set_err(HOTRG_EINVAL, "C_bar launch out of bounds");
+        if (z2) {
+            uint32_t *inv, *roff, *coff;
+            TRY(build_rev_z2(c, cp, Eb, st, zN, zKc, &inv, &roff, &coff));
+            c->z2_rev_steps++;
+            launch_z2_cbar(Tbar, inv, roff, coff, zN[0], zN[1], 1.0 / cp.c, Cbar, CbarT, c->stream);
+            TRY(check_launch(c, "C_bar class blocks"));
+        }
+    }
+    if (z2) {
+        // class buffers: C_bar_g (and transposes) packed for the bf16x3 GEMMs,
+        // transposed class operands (rows K_b, row length zld[g]), GEMM outputs
+        const uint32_t Nmax = std::max(zN[0], zN[1]);
+        for (int g = 0; g < 2; ++g) zld[g] = mixed ? ((uint64_t)zN[g] + 63) / 64 * 64 : zN[g];
+        const uint64_t ldmax = std::max<uint64_t>(std::max(zld[0], zld[1]), 1);
+        if ((uint64_t)Nmax * ldmax >= (1ull << 31) || (uint64_t)std::max(zKc[0], zKc[1]) * ldmax >= (1ull << 31))
+            return set_err(HOTRG_ENOMEM, "reverse pass: class operand exceeds 2^31 elements");
+        if (mixed) {
+            uint64_t cpk[2], need = 0;
+            for (int g = 0; g < 2; ++g) {
+                cpk[g] = packed_rows(zN[g]) * zld[g];
+                need += cpk[g];
+            }
+            uint16_t *zc;
+            TRY(bw_buf(c, BW_ZC, 4 * need, &zc));
+            uint64_t o = 0;
+            for (int g = 0; g < 2; ++g) {
+                zCh[g] = zc + o;
+                zCl[g] = zc + need + o;
+                zCTh[g] = zc + 2 * need + o;
+                zCTl[g] = zc + 3 * need + o;
+                o += cpk[g];
+            }
+            const uint64_t sq0 = (uint64_t)zN[0] * zN[0];
+            for (int g = 0; g < 2; ++g) {
+                if (zN[g] == 0) continue;
+                launch_split_pack(Cbar + (g ? sq0 : 0), zN[g], zN[g], (uint32_t)zld[g], zCh[g], zCl[g], c->stream);
+                launch_split_pack(CbarT + (g ? sq0 : 0), zN[g], zN[g], (uint32_t)zld[g], zCTh[g], zCTl[g],
+                                  c->stream);
+            }
+            uint64_t tpk[2], tneed = 0;
+            for (int b = 0; b < 2; ++b) {
+                tpk[b] = packed_rows(zKc[b]) * ldmax;
+                tneed += tpk[b];
+            }
+            uint16_t *zt;
+            TRY(bw_buf(c, BW_ZT, 4 * tneed, &zt));
+            // padding columns of a block are never written in a slice whose
+            // class row is shorter; they meet zero padding of C_bar, but must
+            // hold finite values
+            HIP_TRY(c, hipMemsetAsync(zt, 0, sizeof(uint16_t) * 4 * tneed, c->stream));
+            for (int b = 0; b < 2; ++b) {
+                const uint64_t o2 = b ? tpk[0] : 0;
+                zATh[b] = zt + o2;
+                zATl[b] = zt + tneed + o2;
+                zBTh[b] = zt + 2 * tneed + o2;
+                zBTl[b] = zt + 3 * tneed + o2;
+            }
+        } else {
+            double *zt;
+            TRY(bw_buf(c, BW_ZT, 2 * (uint64_t)Ks * ldmax, &zt));
+            zAT[0] = zt;
+            zAT[1] = zt + (uint64_t)zKc[0] * ldmax;
+            zBT[0] = zt + (uint64_t)Ks * ldmax;
+            zBT[1] = zBT[0] + (uint64_t)zKc[0] * ldmax;
+        }
+        double *zo;
+        TRY(bw_buf(c, BW_ZO, 2 * (uint64_t)Nmax * Ks, &zo));
+        zAo[0] = zo;
+        zAo[1] = zo + (uint64_t)Nmax * zKc[0];
+        zBo[0] = zo + (uint64_t)Nmax * Ks;
+        zBo[1] = zBo[0] + (uint64_t)Nmax * zKc[0];
+        TRY(check_launch(c, "C_bar class splits"));
+    } else {
+        const int ext[8] = {ka, kb, Dm, kc, ka, kb, Dm, kc};
+        int Dn[4];
+        for (int q = 0; q < 4; ++q) Dn[q] = D[q];
+        for (int i = 0; i < 3; ++i) Dn[tv[i]] = cp.k[i];
+        uint64_t ncs[8];
+        canon_strides(Dn, ncs);
+        uint32_t st[8] = {(uint32_t)ncs[2 * tv[0]], (uint32_t)ncs[2 * tv[1]], (uint32_t)ncs[2 * mu],
+                          (uint32_t)ncs[2 * tv[2]], (uint32_t)ncs[2 * tv[0] + 1], (uint32_t)ncs[2 * tv[1] + 1],
+                          (uint32_t)ncs[2 * mu + 1], (uint32_t)ncs[2 * tv[2] + 1]};
+        uint64_t mx;
+        PermParams pp = perm_params(8, ext, st, &mx);
         launch_permute(pp, Tbar, Cbar, 1.0 / cp.c, c->stream);
         uint32_t stT[8] = {st[4], st[5], st[6], st[7], st[0], st[1], st[2], st[3]};
         pp = perm_params(8, ext, stT, &mx);
@@ -1727,6 +1951,9 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
             const uint64_t offA = f * lst[1] + g * lst[7] + e0 * lst[3];
             const uint64_t offB = g * lst[6];
             const uint64_t uboff = (uint64_t)e0 * Db * kb;  // rows (b1' = e0, b2') of Ub
+            // parity of the indices the slice fixes (alpha, a1', and b1' when Eb = 1)
+            const uint32_t zs =
+                z2 ? (uint32_t)(cp.par[mu][g] ^ cp.par[tv[0]][f] ^ (Eb == 1 ? cp.par[tv[1]][e0] : 0)) : 0u;
             // ---- recompute the forward intermediates and the operands, transposed ([K][rows])
             {
                 XP x;  // P1
@@ -1766,7 +1993,10 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 x.loops(kc, 1, 1, Dc, kc, ldM);
                 x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
                 if (!x.fits(c->cap, usz[2], ldM * Ks)) return set_err(HOTRG_EINVAL, "bw P3 out of bounds");
-                if (mixed) {
+                if (z2) {
+                    TRY(z2t_scatter(c, x, M, Ks, zs, zN, zKc, zld, mixed, zAT, zATh, zATl));
+                    launch_iso_expand(x.done(), Y2, Uc, nullptr, nullptr, nullptr, c->stream);
+                } else if (mixed) {
                     x.packed(ldM);
                     launch_iso_expand(x.done(), Y2, Uc, nullptr, ATh, ATl, c->stream);
                 } else {
@@ -1812,7 +2042,10 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 x.loops(kc, 1, 1, Dc, (uint64_t)Dc * kc, ks1 * ldM);
                 x.sum(Dc, z2s[7], kc);
                 if (!x.fits(c->cap, usz[2], ldM * Ks)) return set_err(HOTRG_EINVAL, "bw Q3 out of bounds");
-                if (mixed) {
+                if (z2) {
+                    TRY(z2t_scatter(c, x, M, Ks, zs, zN, zKc, zld, mixed, zBT, zBTh, zBTl));
+                    launch_iso_expand(x.done(), Z2, Uc, nullptr, nullptr, nullptr, c->stream);
+                } else if (mixed) {
                     x.packed(ldM);
                     launch_iso_expand(x.done(), Z2, Uc, nullptr, BTh, BTl, c->stream);
                 } else {
@@ -1820,7 +2053,37 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 }
             }
             // ---- A_bar = C_bar B, B_bar = C_bar^T A (FP64, or bf16x3 in mixed precision)
-            if (mixed) {
+            if (z2) {
+                // per inner K class b (GEMM class g = b ^ zs): A_bar_b = C_bar_g B_b,
+                // B_bar_b = C_bar_g^T A_b, outputs N_g x K_b; then the natural layout
+                const uint64_t sq0 = (uint64_t)zN[0] * zN[0];
+                X3Gemm ga[2], gb[2];
+                int n = 0;
+                for (int b = 0; b < 2; ++b) {
+                    const int g = b ^ (int)zs;
+                    if (zN[g] == 0 || zKc[b] == 0) continue;
+                    if (mixed) {
+                        ga[n] = X3Gemm{zCh[g], zCl[g], zBTh[b], zBTl[b], zAo[b], (int)zN[g], 1, (int)zKc[b],
+                                       (int)zld[g], zKc[b], 0};
+                        gb[n] = X3Gemm{zCTh[g], zCTl[g], zATh[b], zATl[b], zBo[b], (int)zN[g], 1, (int)zKc[b],
+                                       (int)zld[g], zKc[b], 0};
+                        ++n;
+                    } else {
+                        launch_gemm_f64(Cbar + (g ? sq0 : 0), zBT[b], zAo[b], (int)zN[g], (int)zKc[b], (int)zN[g],
+                                        zN[g], zld[g], zKc[b], 0, c->stream);
+                        launch_gemm_f64(CbarT + (g ? sq0 : 0), zAT[b], zBo[b], (int)zN[g], (int)zKc[b], (int)zN[g],
+                                        zN[g], zld[g], zKc[b], 0, c->stream);
+                    }
+                }
+                if (mixed && n > 0) {
+                    launch_gemm_bf16x3_multi(ga, n, c->stream, tail);
+                    launch_gemm_bf16x3_multi(gb, n, c->stream, tail);
+                }
+                launch_z2_unscatter(zAo[0], zAo[1], zKc[0], zKc[1], c->rtab, c->ktab, zs, 0u, (uint32_t)Ks,
+                                    (uint32_t)M, Abar, c->stream);
+                launch_z2_unscatter(zBo[0], zBo[1], zKc[0], zKc[1], c->rtab, c->ktab, zs, 0u, (uint32_t)Ks,
+                                    (uint32_t)M, Bbar, c->stream);
+            } else if (mixed) {
                 launch_gemm_bf16x3(Ch, Cl, BTh, BTl, Abar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream, tail);
                 launch_gemm_bf16x3(CTh, CTl, ATh, ATl, Bbar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream, tail);
             } else {
@@ -2525,16 +2788,16 @@ int hotrg_get_spectrum(hotrg_ctx *c, int q, int side, double *out, size_t count,
 }
 
 int hotrg_kernel_stats(hotrg_ctx *c, int kernel, double *ms, long long *launches, double *flops) {
-    if (!c || kernel < 0 || kernel > 4) return set_err(HOTRG_EINVAL, "bad argument");
+    if (!c || kernel < 0 || kernel > 5) return set_err(HOTRG_EINVAL, "bad argument");
     if (kernel == 0) {
         if (ms) *ms = c->gemm_ms;
         if (launches) *launches = c->gemm_launches;
         if (flops) *flops = c->gemm_flops;
         return HOTRG_OK;
     }
-    if (kernel == 4) {
+    if (kernel == 4 || kernel == 5) {
         if (ms) *ms = 0.0;
-        if (launches) *launches = c->z2_tile_launches;
+        if (launches) *launches = kernel == 4 ? c->z2_tile_launches : c->z2_rev_steps;
         if (flops) *flops = 0.0;
         return HOTRG_OK;
     }
@@ -2554,6 +2817,7 @@ int hotrg_reset_stats(hotrg_ctx *c) {
     c->gemm_launches = 0;
     c->gemm_flops = 0;
     c->z2_tile_launches = 0;
+    c->z2_rev_steps = 0;
     return HOTRG_OK;
 }
 

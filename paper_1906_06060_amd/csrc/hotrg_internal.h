@@ -67,6 +67,8 @@ struct ExpandParams {
     // K position; FP64 blocks are row-major with row length zld_out[i], bf16
     // blocks packed with zpkb[i] = zld_out[i] / 32 k blocks per row tile.
     int z2;
+    // z2 == 4: the transposed scatter of the reverse pass (see
+    // iso_expand_z2t_kernel; zrs = K step of the second loop).
     // z2 == 2: the run form (see iso_expand_z2run_kernel): the first loop
     // steps whole rows (o1 = zrs * zld), the second stays inside the row
     // (o2 < zld and no carry out of the K part), so a thread needs one row
@@ -155,6 +157,17 @@ struct PermParams {
 void launch_init_site(double *T, double *S, double w00, double w01, double w10, double w11,
                       double v_up, double v_dn, hipStream_t s);
 void launch_permute(const PermParams &p, const double *in, double *out, double scale, hipStream_t s);
+// Reverse pass, Z2 block form (pure T): C_bar class blocks C_g (N_g x N_g,
+// C_0 then C_1, row-major) and their transposes from Tbar; inv lists the
+// natural GEMM rows of class 0 then class 1, roff / coff give a row's / a
+// column's offset in Tbar.
+void launch_z2_cbar(const double *Tbar, const uint32_t *inv, const uint32_t *roff, const uint32_t *coff,
+                    uint32_t N0, uint32_t N1, double scale, double *Cg, double *CgT, hipStream_t s);
+// class-block GEMM outputs (block b: rows = class positions of the rows, row
+// length ldb) -> natural R x Ks operand adjoint with exact zeros elsewhere
+void launch_z2_unscatter(const double *b0, const double *b1, uint32_t ld0, uint32_t ld1, const uint32_t *rtab,
+                         const uint32_t *ktab, uint32_t zs, uint32_t zP, uint32_t Ks, uint32_t R, double *out,
+                         hipStream_t s);
 // dst[j] = src[idx[j]], or 0 where idx[j] < 0, for j < n
 void launch_gather_or_zero(const double *src, const int32_t *idx, double *dst, int n, hipStream_t s);
 // compacted summed-index count the z2 tile kernel is compiled for, given the

@@ -596,6 +596,137 @@ __global__ void __launch_bounds__(Z2TILE_MAX_THREADS) iso_expand_z2tile_kernel(E
     }
 }
 
+// Transposed Z2 block scatter of the reverse pass (z2 == 4): the natural
+// offset o = K zld + r of a transposed operand slice (rows = inner K indices,
+// columns = GEMM rows r) is split into (K, r); the thread's first loop steps
+// r by o1 (< zld), the second steps K by o2 / zld.  An output with K class b
+// goes to block b (GEMM class g = b ^ zs) and is structurally zero unless the
+// parity of r is zP ^ g; block b gets row = K position, column = zrow_off[g] +
+// r position (FP64 row-major with row length zld_out[b], or bf16 hi / lo in the
+// packed layout with zpkb[b] = zld_out[b] / 32).  Same arithmetic as
+// iso_expand_kernel.
+template <bool SPLIT, int N>
+__global__ void __launch_bounds__(kThreads) iso_expand_z2t_kernel(ExpandParams p, const double *__restrict__ in,
+                                                                  const double *__restrict__ U) {
+    extern __shared__ double sZ[];  // [L1][N][N]
+    const int nU = p.L1 * N * N;
+    for (int idx = threadIdx.x; idx < nU; idx += blockDim.x) {
+        const int i = idx % N, l2 = (idx / N) % N, l1 = idx / (N * N);
+        sZ[idx] = U[l1 * p.u1 + l2 * p.u2 + i * p.us];
+    }
+    __syncthreads();
+    const uint32_t kstep = p.zrs;  // K step of the second loop
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < p.threads; t += gridDim.x * blockDim.x) {
+        uint32_t rem = t, ib = 0, ob = 0;
+        for (int k = p.nd - 1; k >= 0; --k) {
+            uint32_t q = fast_div(rem, p.ext[k]);
+            uint32_t c = rem - q * p.ext[k].d;
+            ib += c * p.in_st[k];
+            ob += c * p.out_st[k];
+            rem = q;
+        }
+        const uint32_t K0 = fast_div(ob, p.zld);
+        const uint32_t r0 = ob - K0 * p.zld.d;
+        uint32_t kt[N];
+#pragma unroll
+        for (int l2 = 0; l2 < N; ++l2) kt[l2] = p.ktab[K0 + l2 * kstep];
+        double v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = in[ib + i * p.xs];
+        for (int l1 = 0; l1 < p.L1; ++l1) {
+            const uint32_t rt = p.rtab[r0 + l1 * p.o1];
+            const double *ul = sZ + l1 * N * N;
+#pragma unroll
+            for (int l2 = 0; l2 < N; ++l2) {
+                const uint32_t blk = kt[l2] >> 31, g = blk ^ p.zs;
+                if ((rt >> 31) != (p.zP ^ g)) continue;  // structurally zero
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc = fma(ul[l2 * N + i], v[i], acc);
+                const uint32_t row = kt[l2] & ~Z2_PAR, col = p.zrow_off[g] + (rt & ~Z2_PAR);
+                if (SPLIT) {
+                    const uint16_t h = bf16_bits((float)acc);
+                    const size_t po = ((size_t)(row / PACK_ROWS) * p.zpkb[blk] + col / PACK_K) * (PACK_ROWS * PACK_K) +
+                                      (row % PACK_ROWS) * PACK_K + col % PACK_K;
+                    p.zhi[blk][po] = h;
+                    p.zlo[blk][po] = bf16_bits((float)(acc - bf16_value(h)));
+                } else {
+                    p.zout[blk][(size_t)row * p.zld_out[blk] + col] = acc;
+                }
+            }
+        }
+    }
+}
+
+template <int N>
+void launch_iso_expand_z2t(const ExpandParams &p, bool split, const double *in, const double *U, hipStream_t s) {
+    const size_t lds = (size_t)p.L1 * N * N * sizeof(double);
+    const int g = grid_for(p.threads, kThreads, 4096);
+    if (split) iso_expand_z2t_kernel<true, N><<<g, kThreads, lds, s>>>(p, in, U);
+    else iso_expand_z2t_kernel<false, N><<<g, kThreads, lds, s>>>(p, in, U);
+}
+
+// C_bar in class blocks (reverse pass, pure T): for class g, rows and columns
+// are the natural GEMM rows of parity g (inv lists them in class order);
+// C_g[i][j] = scale * Tbar[roff[inv_g[i]] + coff[inv_g[j]]], and its transpose.
+__global__ void __launch_bounds__(kThreads) z2_cbar_kernel(const double *__restrict__ Tbar,
+                                                          const uint32_t *__restrict__ inv,
+                                                          const uint32_t *__restrict__ roff,
+                                                          const uint32_t *__restrict__ coff, uint32_t N0,
+                                                          FastDiv n0, FastDiv n1, double scale,
+                                                          double *__restrict__ Cg, double *__restrict__ CgT) {
+    const uint32_t N1 = n1.d, tot0 = N0 * N0, tot = tot0 + N1 * N1;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
+        const bool g1 = e >= tot0;
+        const uint32_t loc = g1 ? e - tot0 : e;
+        const FastDiv &nd = g1 ? n1 : n0;
+        const uint32_t i = fast_div(loc, nd), j = loc - i * nd.d;
+        const uint32_t *iv = inv + (g1 ? N0 : 0);
+        const double v = scale * Tbar[roff[iv[i]] + coff[iv[j]]];
+        const size_t base = g1 ? tot0 : 0;
+        Cg[base + (size_t)i * nd.d + j] = v;
+        CgT[base + (size_t)j * nd.d + i] = v;
+    }
+}
+
+void launch_z2_cbar(const double *Tbar, const uint32_t *inv, const uint32_t *roff, const uint32_t *coff,
+                    uint32_t N0, uint32_t N1, double scale, double *Cg, double *CgT, hipStream_t s) {
+    const size_t tot = (size_t)N0 * N0 + (size_t)N1 * N1;
+    if (tot == 0) return;
+    z2_cbar_kernel<<<grid_for(tot), kThreads, 0, s>>>(Tbar, inv, roff, coff, N0, make_fastdiv(N0 ? N0 : 1),
+                                                      make_fastdiv(N1 ? N1 : 1), scale, Cg, CgT);
+}
+
+// Class-block GEMM outputs -> natural [R][Ks] operand adjoint (reverse pass):
+// out[r][K] = blk_b[pos(r) * ldb[b] + pos(K)] when the parity of r is
+// zP ^ b ^ zs (b the class of K), else exactly 0.
+__global__ void __launch_bounds__(kThreads) z2_unscatter_kernel(const double *__restrict__ b0,
+                                                               const double *__restrict__ b1, uint32_t ld0,
+                                                               uint32_t ld1, const uint32_t *__restrict__ rtab,
+                                                               const uint32_t *__restrict__ ktab, uint32_t zs,
+                                                               uint32_t zP, FastDiv ks, uint32_t R,
+                                                               double *__restrict__ out) {
+    const size_t tot = (size_t)R * ks.d;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
+        const uint32_t r = fast_div(e, ks), k = e - r * ks.d;
+        const uint32_t kt = ktab[k], rt = rtab[r];
+        const uint32_t b = kt >> 31;
+        double v = 0.0;
+        if ((rt >> 31) == (zP ^ b ^ zs))
+            v = b ? b1[(size_t)(rt & ~Z2_PAR) * ld1 + (kt & ~Z2_PAR)] : b0[(size_t)(rt & ~Z2_PAR) * ld0 + (kt & ~Z2_PAR)];
+        out[e] = v;
+    }
+}
+
+void launch_z2_unscatter(const double *b0, const double *b1, uint32_t ld0, uint32_t ld1, const uint32_t *rtab,
+                         const uint32_t *ktab, uint32_t zs, uint32_t zP, uint32_t Ks, uint32_t R, double *out,
+                         hipStream_t s) {
+    const size_t tot = (size_t)R * Ks;
+    if (tot == 0) return;
+    z2_unscatter_kernel<<<grid_for(tot), kThreads, 0, s>>>(b0, b1, ld0, ld1, rtab, ktab, zs, zP, make_fastdiv(Ks), R,
+                                                           out);
+}
+
 // tU[j] = src[idx[j]] (0 where idx[j] < 0)
 __global__ void gather_or_zero_kernel(const double *__restrict__ src, const int32_t *__restrict__ idx,
                                       double *__restrict__ dst, int n) {
@@ -782,6 +913,26 @@ void launch_iso_expand_pairs(const ExpandParams &p, bool run, const double *in, 
 void launch_iso_expand(const ExpandParams &pin, const double *in, const double *U, double *out, uint16_t *hi,
                        uint16_t *lo, hipStream_t s) {
     if (pin.threads == 0) return;
+    if (pin.z2 == 4) {
+        // transposed block scatter; the host checks nsum == L2 <= 13 and the LDS size
+        const bool split = pin.zhi[0] != nullptr;
+        switch (pin.L2) {
+            case 1: return launch_iso_expand_z2t<1>(pin, split, in, U, s);
+            case 2: return launch_iso_expand_z2t<2>(pin, split, in, U, s);
+            case 3: return launch_iso_expand_z2t<3>(pin, split, in, U, s);
+            case 4: return launch_iso_expand_z2t<4>(pin, split, in, U, s);
+            case 5: return launch_iso_expand_z2t<5>(pin, split, in, U, s);
+            case 6: return launch_iso_expand_z2t<6>(pin, split, in, U, s);
+            case 7: return launch_iso_expand_z2t<7>(pin, split, in, U, s);
+            case 8: return launch_iso_expand_z2t<8>(pin, split, in, U, s);
+            case 9: return launch_iso_expand_z2t<9>(pin, split, in, U, s);
+            case 10: return launch_iso_expand_z2t<10>(pin, split, in, U, s);
+            case 11: return launch_iso_expand_z2t<11>(pin, split, in, U, s);
+            case 12: return launch_iso_expand_z2t<12>(pin, split, in, U, s);
+            case 13: return launch_iso_expand_z2t<13>(pin, split, in, U, s);
+            default: return;
+        }
+    }
     if (pin.z2) {
         // the host checks nsum == L2 <= 13 and the LDS size (z2_expand_ok)
         const bool split = pin.zhi[0] != nullptr;

@@ -337,6 +337,13 @@ class Context:
         _check(_lib.hotrg_kernel_stats(self._h, 4, None, C.byref(ln), None))
         return ln.value
 
+    def z2_reverse_steps(self):
+        """Reverse-pass steps since the last reset undone in the Z2 block form
+        (hotrg_kernel_stats kernel 5)."""
+        ln = C.c_longlong()
+        _check(_lib.hotrg_kernel_stats(self._h, 5, None, C.byref(ln), None))
+        return ln.value
+
     def phase_stats(self):
         """Device ms per phase of hotrg_step since the last reset (kernels 1..3),
         the GEMM ms (kernel 0) and the number of steps counted."""

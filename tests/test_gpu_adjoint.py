@@ -167,3 +167,32 @@ def test_backward_keeps_z2_exactly_at_zero_field_mixed_precision(H):
     lnz, db, dh = gpu_grad(H, 0.1497, 0.0, 6, 8, precision=H.BF16X3, mixed_from_step=4)
     assert dh == 0.0
     assert math.isfinite(db) and db > 0
+
+
+@pytest.mark.parametrize("precision,rel", [("FP64", 1e-10), ("BF16X3", 3e-4)])
+@pytest.mark.parametrize("budget", [0, 1])
+def test_backward_block_form_equals_dense_reverse(H, precision, rel, budget):
+    # at h = 0 the steps that contracted in the Z2 block form are undone in it
+    # (class GEMMs on the class blocks of C_bar and of the recomputed
+    # operands, with and without K slices that fix b1'); the same flow with
+    # dense_only contracts and reverses every step densely.  The derivatives
+    # agree to rounding (FP64) or to the bf16x3 bound used against FP64, and
+    # dlnZ/dh is exactly 0 in both
+    beta, dcut, n = 0.1497, 6, 8
+    prec = getattr(H, precision)
+    out = {}
+    for dense in (False, True):
+        with H.Context(beta, 0.0, dcut, keep_checkpoints=True, impurities=False, precision=prec,
+                       slice_budget=budget, dense_only=dense) as ctx:
+            blocks = 0
+            for k in range(n):
+                ctx.step(k % 4)
+                blocks += ctx.observables()["block_sparse"]
+            lnz = ctx.lnz()
+            db, dh = ctx.backward()
+            out[dense] = (lnz, db, dh, ctx.z2_reverse_steps(), blocks)
+    a, b = out[False], out[True]
+    assert a[4] >= n - 1 and a[3] == a[4] and b[3] == 0 and b[4] == 0
+    assert a[0] == pytest.approx(b[0], rel=1e-6 if precision == "BF16X3" else 1e-12)
+    assert a[1] == pytest.approx(b[1], rel=rel)
+    assert a[2] == 0.0 and b[2] == 0.0
