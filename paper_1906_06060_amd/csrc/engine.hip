@@ -113,19 +113,25 @@ struct hotrg_ctx {
     long long gemm_launches = 0;
     long long z2_tile_launches = 0;  // last isometry products run in the tile form of the Z2 scatter
     long long z2_rev_steps = 0;      // reverse-pass steps undone in the Z2 block form
-    // tile form of the Z2 scatter, per last product (0: A rows, 1: B rows):
-    // the slot table and the permuted isometry block, rebuilt once per set of
-    // class tables (z2_gen counts build_z2_tables calls)
-    long long z2_gen = 0, tile_gen[2] = {-1, -1};
-    std::vector<uint32_t> tperm_h[2];
-    std::vector<int32_t> tidx_h[2];  // compacted isometry block: source offsets (-1: zero)
-    uint32_t *tperm_d[2] = {nullptr, nullptr};
-    int32_t *tidx_d[2] = {nullptr, nullptr};
-    double *tU_d[2] = {nullptr, nullptr};
-    uint32_t tslots[2] = {0, 0};
-    int tNH[2] = {0, 0};
-    uint32_t tlab1[2] = {0, 0}, tlab2[2] = {0, 0}, tnI[2][2] = {{0, 0}, {0, 0}};
-    uint64_t tI[2][2] = {{0, 0}, {0, 0}};
+    // tile form of the Z2 scatter, per last product (0: A rows, 1: B rows of
+    // the forward; 2, 3: the transposed A, B operands of the reverse pass):
+    // the slot table and the compacted isometry block, rebuilt once per set of
+    // class tables (z2_gen counts the table builds)
+    long long z2_gen = 0, tile_gen[4] = {-1, -1, -1, -1};
+    std::vector<uint32_t> tperm_h[4];
+    std::vector<int32_t> tidx_h[4];  // compacted isometry block: source offsets (-1: zero)
+    uint32_t *tperm_d[4] = {};
+    int32_t *tidx_d[4] = {};
+    double *tU_d[4] = {};
+    uint32_t tslots[4] = {};
+    int tNH[4] = {};
+    uint32_t tlab1[4] = {}, tlab2[4] = {}, tnI[4][2] = {};
+    uint64_t tI[4][2] = {};
+    // reverse pass, block form: the inner K indices of the transposed B
+    // operand in the order (b1', a2, b2, c2, c1') (host / device), and its
+    // entries listed in the dense order (the A_bar table)
+    std::vector<uint32_t> ktabq_h, kmapq_h;
+    uint32_t *ktabq = nullptr, *kmapq = nullptr;
     double gemm_flops = 0;
     size_t device_bytes = 0;
     // phase timing of hotrg_step: events at the start, after the isometries,
@@ -666,9 +672,11 @@ int build_z2_tables(hotrg_ctx *c, int mu, const int tv[3], const int k[3], int E
 // class tables changed) and returns false, so that the run form is used,
 // when the layout does not match or a limit is exceeded.
 int z2_tile_plan(hotrg_ctx *c, ExpandParams &p, const double *U, uint64_t threads, int nko, int nro, uint64_t Ks,
-                 int id, const std::vector<uint8_t> *labs, bool *ok) {
+                 int id, const std::vector<uint8_t> *labs, const std::vector<uint32_t> &kt, bool *ok) {
+    // (Ks: the natural row length, i.e. the number of columns; kt: the host
+    // copy of the column table)
     *ok = false;
-    if (id < 0 || id > 1 || nko < 0 || nro < 0 || nko + nro > p.nd || p.o1 != Ks || !labs) return HOTRG_OK;
+    if (id < 0 || id > 3 || nko < 0 || nro < 0 || nko + nro > p.nd || p.o1 != Ks || !labs) return HOTRG_OK;
     // parity labels of the summed index, the first and the second loop index
     if ((int)labs[0].size() != p.nsum || (int)labs[1].size() != p.L1 || (int)labs[2].size() != p.L2 ||
         p.nsum > 13 || p.L1 > 13 || p.L2 > 13)
@@ -705,7 +713,6 @@ int z2_tile_plan(hotrg_ctx *c, ExpandParams &p, const double *U, uint64_t thread
         NRP *= p.ext[d].d;
     }
     if (P == 0 || NRP * Kg * P != threads) return HOTRG_OK;
-    const auto &kt = c->ktab_h;
     if (kt.size() != Ks) return HOTRG_OK;
     // largest class share of one K group
     uint64_t maxnk = 0;
@@ -840,7 +847,7 @@ int z2_scatter(hotrg_ctx *c, XP &x, const double *U, uint64_t Ks, uint32_t zs, u
     }
     if (mixed && p.z2 == 2 && (((uintptr_t)hi[0] | (uintptr_t)hi[1] | (uintptr_t)lo[0] | (uintptr_t)lo[1]) & 15) == 0) {
         bool ok = false;
-        TRY(z2_tile_plan(c, p, U, x.threads, nko, nro, Ks, tile_id, labs, &ok));
+        TRY(z2_tile_plan(c, p, U, x.threads, nko, nro, Ks, tile_id, labs, c->ktab_h, &ok));
         if (ok) {
             p.z2 = 3;
             c->z2_tile_launches++;
@@ -1661,10 +1668,33 @@ int build_rev_z2(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, int Eb, const ui
         N[g] = cnt[g];
         Kc[g] = kcnt[g];
     }
+    // the transposed B operand orders its K indices (b1', a2, b2, c2, c1') (its
+    // product steps c1'); kmapq lists those entries by dense index
+    auto &kq = c->ktabq_h;
+    auto &km = c->kmapq_h;
+    kq.resize(Ks);
+    km.resize(Ks);
+    {
+        uint32_t qc[2] = {0, 0}, kk2 = 0;
+        for (int b1 = 0; b1 < Eb; ++b1)
+            for (int a2 = 0; a2 < Da; ++a2)
+                for (int b2 = 0; b2 < Db; ++b2)
+                    for (int c2 = 0; c2 < Dc; ++c2)
+                        for (int c1 = 0; c1 < Dc; ++c1) {
+                            const int p = (Eb == Db ? ob[b1] : 0) ^ oc[c1] ^ oa[a2] ^ ob[b2] ^ oc[c2];
+                            const uint32_t e = (p ? Z2_PAR : 0u) | qc[p]++;
+                            kq[kk2++] = e;
+                            km[(((size_t)b1 * Dc + c1) * Da + a2) * Db * Dc + (size_t)b2 * Dc + c2] = e;
+                        }
+    }
     const size_t Dmax = (size_t)std::max(c->dcut, 2);
     if (!c->rtab) TRY(alloc_n(c, &c->rtab, Dmax * Dmax * Dmax * Dmax));
     if (!c->ktab) TRY(alloc_n(c, &c->ktab, Dmax * Dmax * Dmax * Dmax * Dmax));
+    if (!c->ktabq) TRY(alloc_n(c, &c->ktabq, Dmax * Dmax * Dmax * Dmax * Dmax));
+    if (!c->kmapq) TRY(alloc_n(c, &c->kmapq, Dmax * Dmax * Dmax * Dmax * Dmax));
     if (!c->rev_tabs) TRY(alloc_n(c, &c->rev_tabs, 3 * Dmax * Dmax * Dmax * Dmax));
+    HIP_TRY(c, hipMemcpyAsync(c->ktabq, kq.data(), sizeof(uint32_t) * Ks, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->kmapq, km.data(), sizeof(uint32_t) * Ks, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->rtab, rt.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->ktab, kt.data(), sizeof(uint32_t) * Ks, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->rev_tabs, hv.data(), sizeof(uint32_t) * hv.size(), hipMemcpyHostToDevice,
@@ -1679,13 +1709,58 @@ int build_rev_z2(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, int Eb, const ui
 }
 
 // Transposed block scatter of a reverse-pass operand product (natural offset
-// o = K M + r): checks that the thread dims split into K digits (strides
-// multiples of M) and row digits (strides below M) without carries, and sets
-// the block outputs (block b: rows K_b, row length ld[b ^ zs]).
-int z2t_scatter(hotrg_ctx *c, XP &x, uint64_t M, uint64_t Ks, uint32_t zs, const uint32_t N[2], const uint32_t Kc[2],
-                const uint64_t ld[2], bool mixed, double *const out[2], uint16_t *const hi[2],
-                uint16_t *const lo[2]) {
+// o = K M + r; rows = inner K indices in the order of the row table ktab_d,
+// columns = GEMM rows r): block b gets rows K_b, row length ld[b ^ zs].
+// bf16 outputs use the tile form of the forward scatter with the roles of the
+// tables exchanged (rows = K, columns = r) when x's thread dims are laid out
+// [nko column-outer | nro K-row | column-inner] with the first loop stepping
+// one K row and the second a column run (labs: labels of the summed index,
+// the first and the second loop index); otherwise the loops are exchanged back
+// and the element scatter runs, after checks that the thread dims split into
+// K digits (strides multiples of M) and row digits (strides below M) without
+// carries.
+int z2t_scatter(hotrg_ctx *c, XP &x, const double *U, uint64_t M, uint64_t Ks, uint32_t zs, const uint32_t N[2],
+                const uint32_t Kc[2], const uint64_t ld[2], bool mixed, double *const out[2], uint16_t *const hi[2],
+                uint16_t *const lo[2], const uint32_t *ktab_d, int tile_id, int nko, int nro,
+                const std::vector<uint8_t> *labs) {
     ExpandParams &p = x.p;
+    for (int b = 0; b < 2; ++b)
+        if (ld[b ^ zs] < N[b ^ zs]) return set_err(HOTRG_EINVAL, "reverse Z2 scatter: block row too short");
+    (void)Kc;
+    p.zld = make_fastdiv((uint32_t)M);
+    p.zs = zs;
+    p.zP = 0;
+    // (the tile kernel needs the column run loop as long as the summed index)
+    if (mixed && tile_id >= 2 && p.o1 == M && p.nsum == p.L2 && p.L1 <= 13 &&
+        (((uintptr_t)hi[0] | (uintptr_t)hi[1] | (uintptr_t)lo[0] | (uintptr_t)lo[1]) & 15) == 0) {
+        // rows: K (row table ktab_d, Kc per class); columns: r (rtab, N per class);
+        // the kernel's block b (columns of class b) is our block b ^ zs
+        p.rtab = ktab_d;
+        p.ktab = c->rtab;
+        p.zM = (uint32_t)Ks;
+        for (int b = 0; b < 2; ++b) {
+            p.zNr[b] = Kc[b];
+            p.zKc[b] = N[b];
+            p.zrow_off[b] = 0;
+            p.zld_out[b] = (uint32_t)ld[b];
+            p.zpkb[b] = (uint32_t)(ld[b] / PACK_K);
+            p.zout[b] = nullptr;
+            p.zhi[b] = hi[b ^ zs];
+            p.zlo[b] = lo[b ^ zs];
+        }
+        bool ok = false;
+        TRY(z2_tile_plan(c, p, U, x.threads, nko, nro, M, tile_id, labs, c->rtab_h, &ok));
+        if (ok) {
+            p.z2 = 3;
+            c->z2_tile_launches++;
+            return HOTRG_OK;
+        }
+    }
+    if (p.o1 == M) {  // back to (column step, K step) loops for the element scatter
+        std::swap(p.L1, p.L2);
+        std::swap(p.u1, p.u2);
+        std::swap(p.o1, p.o2);
+    }
     if (p.nsum != p.L2 || p.L2 > 13 || (size_t)p.L1 * p.L2 * p.L2 * sizeof(double) > 48 * 1024)
         return set_err(HOTRG_EINVAL, "reverse Z2 scatter: unsupported product shape");
     if (p.o1 >= M || p.o2 % M != 0) return set_err(HOTRG_EINVAL, "reverse Z2 scatter: unsupported loop strides");
@@ -1697,16 +1772,10 @@ int z2t_scatter(hotrg_ctx *c, XP &x, uint64_t M, uint64_t Ks, uint32_t zs, const
         else return set_err(HOTRG_EINVAL, "reverse Z2 scatter: a thread dim mixes rows and K");
     }
     if (rmax >= M || kmax >= Ks) return set_err(HOTRG_EINVAL, "reverse Z2 scatter: launch out of bounds");
-    for (int b = 0; b < 2; ++b)
-        if (ld[b ^ zs] < N[b ^ zs]) return set_err(HOTRG_EINVAL, "reverse Z2 scatter: block row too short");
-    (void)Kc;
     p.z2 = 4;
     p.zrs = (uint32_t)(p.o2 / M);
-    p.zld = make_fastdiv((uint32_t)M);
     p.rtab = c->rtab;
-    p.ktab = c->ktab;
-    p.zs = zs;
-    p.zP = 0;
+    p.ktab = ktab_d;
     for (int b = 0; b < 2; ++b) {
         const uint32_t g = (uint32_t)b ^ zs;
         p.zrow_off[b] = 0;
@@ -1983,18 +2052,32 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
             {
                 XP x;  // P3 -> A^T [K][M] (row length ldM); the GEMM-row dims innermost, so that
                        // neighbouring lanes write neighbouring columns of A^T
-                x.tdim(Eb, y2s[3], ks0 * ldM);
-                x.tdim(Dc, y2s[4], ks1 * ldM);
-                x.tdim(Da, y2s[5], ks2 * ldM);
-                x.tdim(Db, y2s[6], ks3 * ldM);
-                x.tdim(ka, y2s[0], r0);
-                x.tdim(kb, y2s[1], r1);
-                x.tdim(Dm, y2s[2], r2);
-                x.loops(kc, 1, 1, Dc, kc, ldM);
+                if (z2) {  // tile layout: column-outer (a), K rows (b1', c1', a2, b2 | c2), column-inner (b, mu1 | c)
+                    x.tdim(ka, y2s[0], r0);
+                    x.tdim(Eb, y2s[3], ks0 * ldM);
+                    x.tdim(Dc, y2s[4], ks1 * ldM);
+                    x.tdim(Da, y2s[5], ks2 * ldM);
+                    x.tdim(Db, y2s[6], ks3 * ldM);
+                    x.tdim(kb, y2s[1], r1);
+                    x.tdim(Dm, y2s[2], r2);
+                    x.loops(Dc, kc, ldM, kc, 1, 1);
+                } else {
+                    x.tdim(Eb, y2s[3], ks0 * ldM);
+                    x.tdim(Dc, y2s[4], ks1 * ldM);
+                    x.tdim(Da, y2s[5], ks2 * ldM);
+                    x.tdim(Db, y2s[6], ks3 * ldM);
+                    x.tdim(ka, y2s[0], r0);
+                    x.tdim(kb, y2s[1], r1);
+                    x.tdim(Dm, y2s[2], r2);
+                    x.loops(kc, 1, 1, Dc, kc, ldM);
+                }
                 x.sum(Dc, y2s[7], (uint64_t)Dc * kc);
                 if (!x.fits(c->cap, usz[2], ldM * Ks)) return set_err(HOTRG_EINVAL, "bw P3 out of bounds");
                 if (z2) {
-                    TRY(z2t_scatter(c, x, M, Ks, zs, zN, zKc, zld, mixed, zAT, zATh, zATl));
+                    // labels: summed c1, first loop c2 (old c), second loop c (new c)
+                    const std::vector<uint8_t> labs[3] = {cp.par[tv[2]], cp.par[tv[2]], cp.npar[2]};
+                    TRY(z2t_scatter(c, x, Uc, M, Ks, zs, zN, zKc, zld, mixed, zAT, zATh, zATl, c->ktab, 2, 1, 4,
+                                    labs));
                     launch_iso_expand(x.done(), Y2, Uc, nullptr, nullptr, nullptr, c->stream);
                 } else if (mixed) {
                     x.packed(ldM);
@@ -2032,18 +2115,36 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
             }
             {
                 XP x;  // Q3 -> B^T [K][N] (row length ldM); GEMM-row dims innermost as in P3
-                x.tdim(Eb, z2s[3], ks0 * ldM);
-                x.tdim(Da, z2s[4], ks2 * ldM);
-                x.tdim(Db, z2s[5], ks3 * ldM);
-                x.tdim(Dc, z2s[6], ldM);
-                x.tdim(ka, z2s[0], r0);
-                x.tdim(kb, z2s[1], r1);
-                x.tdim(Dm, z2s[2], r2);
-                x.loops(kc, 1, 1, Dc, (uint64_t)Dc * kc, ks1 * ldM);
+                if (z2) {
+                    // K in the order (b1', a2, b2, c2, c1') of ktabq, so that the
+                    // product's c1' loop steps one K row; tile layout: column-outer
+                    // (a'), K rows (b1', a2, b2, c2 | c1'), column-inner (b', mu2' | c')
+                    const uint64_t q3 = Dc, q2 = (uint64_t)Dc * Dc, q1 = q2 * Db, q0 = q1 * Da;
+                    x.tdim(ka, z2s[0], r0);
+                    x.tdim(Eb, z2s[3], q0 * ldM);
+                    x.tdim(Da, z2s[4], q1 * ldM);
+                    x.tdim(Db, z2s[5], q2 * ldM);
+                    x.tdim(Dc, z2s[6], q3 * ldM);
+                    x.tdim(kb, z2s[1], r1);
+                    x.tdim(Dm, z2s[2], r2);
+                    x.loops(Dc, (uint64_t)Dc * kc, ldM, kc, 1, 1);
+                } else {
+                    x.tdim(Eb, z2s[3], ks0 * ldM);
+                    x.tdim(Da, z2s[4], ks2 * ldM);
+                    x.tdim(Db, z2s[5], ks3 * ldM);
+                    x.tdim(Dc, z2s[6], ldM);
+                    x.tdim(ka, z2s[0], r0);
+                    x.tdim(kb, z2s[1], r1);
+                    x.tdim(Dm, z2s[2], r2);
+                    x.loops(kc, 1, 1, Dc, (uint64_t)Dc * kc, ks1 * ldM);
+                }
                 x.sum(Dc, z2s[7], kc);
                 if (!x.fits(c->cap, usz[2], ldM * Ks)) return set_err(HOTRG_EINVAL, "bw Q3 out of bounds");
                 if (z2) {
-                    TRY(z2t_scatter(c, x, M, Ks, zs, zN, zKc, zld, mixed, zBT, zBTh, zBTl));
+                    // labels: summed c2', first loop c1' (old c), second loop c' (new c)
+                    const std::vector<uint8_t> labs[3] = {cp.par[tv[2]], cp.par[tv[2]], cp.npar[2]};
+                    TRY(z2t_scatter(c, x, Uc, M, Ks, zs, zN, zKc, zld, mixed, zBT, zBTh, zBTl, c->ktabq, 3, 1, 4,
+                                    labs));
                     launch_iso_expand(x.done(), Z2, Uc, nullptr, nullptr, nullptr, c->stream);
                 } else if (mixed) {
                     x.packed(ldM);
@@ -2079,7 +2180,8 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                     launch_gemm_bf16x3_multi(ga, n, c->stream, tail);
                     launch_gemm_bf16x3_multi(gb, n, c->stream, tail);
                 }
-                launch_z2_unscatter(zAo[0], zAo[1], zKc[0], zKc[1], c->rtab, c->ktab, zs, 0u, (uint32_t)Ks,
+                // A_bar's columns follow the rows of B^T (ktabq order), B_bar's those of A^T
+                launch_z2_unscatter(zAo[0], zAo[1], zKc[0], zKc[1], c->rtab, c->kmapq, zs, 0u, (uint32_t)Ks,
                                     (uint32_t)M, Abar, c->stream);
                 launch_z2_unscatter(zBo[0], zBo[1], zKc[0], zKc[1], c->rtab, c->ktab, zs, 0u, (uint32_t)Ks,
                                     (uint32_t)M, Bbar, c->stream);
