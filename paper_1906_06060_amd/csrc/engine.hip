@@ -186,6 +186,7 @@ struct hotrg_ctx {
     // reverse-pass work buffers
     DevBuf bw[18];
     uint32_t *rev_tabs = nullptr;  // reverse pass, block form: class lists and Tbar offsets of the rows
+    double *xmv_buf = nullptr;     // reverse pass: the gathered small matrix of a small-matrix product
 };
 
 namespace {
@@ -1587,10 +1588,125 @@ int bw_buf(hotrg_ctx *c, int which, size_t count, T **p) {
 
 constexpr size_t kPartialCap = (size_t)1 << 20;  // doubles of split-sum partials
 
+// A contraction whose every output index addresses only one operand, with
+// few outputs and a long sum, as the outer-product reduction (RedParams);
+// false when it does not have that form.
+bool red_params(const EinsumParams &q, RedParams &r) {
+    if (q.nout == 0 || q.nout > 4096 || q.S < 4096) return false;
+    r = RedParams{};
+    uint32_t Mo = 1, No = 1, xm1 = 0, yn1 = 0;
+    for (int k = 0; k < q.ndo; ++k) {
+        const uint32_t ext = q.oext[k].d;
+        if (ext == 1) continue;
+        if (q.ox[k] != 0 && q.oy[k] == 0) {
+            if (r.ndm >= RED_MAXD) return false;
+            r.mext[r.ndm] = ext;
+            r.mx[r.ndm] = q.ox[k];
+            r.mz[r.ndm] = q.oz[k];
+            ++r.ndm;
+            Mo *= ext;
+            xm1 = q.ox[k];
+        } else if (q.oy[k] != 0 && q.ox[k] == 0) {
+            if (r.ndn >= RED_MAXD) return false;
+            r.next[r.ndn] = ext;
+            r.ny[r.ndn] = q.oy[k];
+            r.nz[r.ndn] = q.oz[k];
+            ++r.ndn;
+            No *= ext;
+            yn1 = q.oy[k];
+        } else {
+            return false;
+        }
+    }
+    r.nds = q.nds;
+    uint32_t sx1 = 0, sy1 = 0;
+    for (int k = 0; k < q.nds; ++k) {
+        r.sext[k] = make_fastdiv(q.sext[k]);
+        r.sx[k] = q.sx[k];
+        r.sy[k] = q.sy[k];
+        if (q.sext[k] > 1) {
+            sx1 = q.sx[k];
+            sy1 = q.sy[k];
+        }
+    }
+    r.mo = make_fastdiv(Mo);
+    r.no = make_fastdiv(No);
+    r.S = q.S;
+    // stage each operand with its smaller-stride index fastest
+    r.xmfast = Mo > 1 && (sx1 == 0 || xm1 < sx1);
+    r.ynfast = No > 1 && (sy1 == 0 || yn1 < sy1);
+    r.alpha = q.alpha;
+    r.accumulate = q.accumulate;
+    return true;
+}
+
+// A contraction with many outputs, a short sum (<= 100 terms) addressing both
+// operands, and output indices that address only X (few) or only Y (many),
+// as the small-matrix product (XmvParams); false otherwise.
+bool xmv_params(const EinsumParams &q, XmvParams &r, bool *swap) {
+    if (q.nout < (1u << 16) || q.S > 100 || q.S == 0) return false;
+    // the small matrix is the operand whose own output indices span fewer values
+    uint64_t px = 1, py = 1;
+    for (int k = 0; k < q.ndo; ++k) {
+        if (q.ox[k] != 0 && q.oy[k] == 0) px *= q.oext[k].d;
+        if (q.oy[k] != 0 && q.ox[k] == 0) py *= q.oext[k].d;
+    }
+    *swap = py < px;
+    const uint32_t *ox = *swap ? q.oy : q.ox, *oy = *swap ? q.ox : q.oy;
+    const uint32_t *sx = *swap ? q.sy : q.sx, *sy = *swap ? q.sx : q.sy;
+    r = XmvParams{};
+    uint32_t M = 1, N = 1;
+    for (int k = 0; k < q.ndo; ++k) {
+        const uint32_t ext = q.oext[k].d;
+        if (ext == 1) continue;
+        if (ox[k] != 0 && oy[k] == 0) {
+            if (r.ndm >= RED_MAXD) return false;
+            r.mext[r.ndm] = ext;
+            r.mx[r.ndm] = ox[k];
+            r.mz[r.ndm] = q.oz[k];
+            ++r.ndm;
+            M *= ext;
+        } else if (oy[k] != 0 && ox[k] == 0) {
+            r.next[r.ndn] = q.oext[k];
+            r.ny[r.ndn] = oy[k];
+            r.nz[r.ndn] = q.oz[k];
+            ++r.ndn;
+            N *= ext;
+        } else {
+            return false;
+        }
+    }
+    if (M > XMV_MAXM) return false;
+    r.nds = q.nds;
+    for (int k = 0; k < q.nds; ++k) {
+        r.sext[k] = q.sext[k];
+        r.sx[k] = sx[k];
+        r.sy[k] = sy[k];
+    }
+    r.M = M;
+    r.N = N;
+    r.K = q.S;
+    r.alpha = q.alpha;
+    r.accumulate = q.accumulate;
+    return true;
+}
+
+constexpr size_t kXmvCap = (size_t)XMV_MAXM * 100;  // doubles of the gathered small matrix
+
 int run_einsum(hotrg_ctx *c, EP &e, const double *X, uint64_t xa, const double *Y, uint64_t ya, double *out,
                uint64_t za, double alpha, int accumulate, const char *what) {
     if (!e.fits(xa, ya, za)) return set_err(HOTRG_EINVAL, std::string(what) + ": launch out of bounds");
-    launch_einsum(e.done(alpha, accumulate), X, Y, out, c->gram_part, kPartialCap, c->stream);
+    const EinsumParams q = e.done(alpha, accumulate);
+    RedParams r;
+    XmvParams xv;
+    if (red_params(q, r) && launch_red(r, X, Y, out, c->gram_part, kPartialCap, c->stream)) return check_launch(c, what);
+    bool swap = false;
+    if (xmv_params(q, xv, &swap)) {
+        if (!c->xmv_buf) TRY(alloc_n(c, &c->xmv_buf, kXmvCap));
+        if (launch_xmv(xv, swap ? Y : X, swap ? X : Y, out, c->xmv_buf, kXmvCap, c->stream))
+            return check_launch(c, what);
+    }
+    launch_einsum(q, X, Y, out, c->gram_part, kPartialCap, c->stream);
     return check_launch(c, what);
 }
 

@@ -130,6 +130,44 @@ struct EinsumParams {
     int accumulate;
 };
 
+// Outer-product reduction of the reverse pass (a contraction whose every
+// output index addresses only one operand):
+//   out[zm(m) + zn(n)] (+)= alpha * sum_k X[x(k) + xm(m)] * Y[y(k) + yn(n)],
+// m over ndm dims (extents mext, strides mx in X, mz in out), n over ndn dims
+// (next, ny, nz), k over nds dims (sext, sx, sy), each row-major.  Mo = prod
+// mext, No = prod next (Mo No <= 4096).  xmfast / ynfast: stage X (Y) with m
+// (n) as the fastest index (else k).
+constexpr int RED_MAXD = 4;
+struct RedParams {
+    int ndm, ndn, nds;
+    uint32_t mext[RED_MAXD], mx[RED_MAXD], mz[RED_MAXD];
+    uint32_t next[RED_MAXD], ny[RED_MAXD], nz[RED_MAXD];
+    FastDiv sext[EIN_MAXS];
+    uint32_t sx[EIN_MAXS], sy[EIN_MAXS];
+    FastDiv mo, no;
+    uint32_t S, chunk, nchunks;
+    int xmfast, ynfast;
+    double alpha;
+    int accumulate;
+};
+
+// Small matrix times many strided columns (reverse pass): a contraction whose
+// summed indices k address both operands and whose output indices split into
+// X-only indices m (ndm dims, M <= 256 values) and Y-only indices n (ndn dims):
+//   out[zm(m) + zn(n)] (+)= alpha * sum_k X[xm(m) + xk(k)] * Y[yn(n) + yk(k)],
+// K = prod sext <= 100 (all rows of the multi-indices row-major).
+constexpr int XMV_MAXM = 256;
+struct XmvParams {
+    int ndm, ndn, nds;
+    uint32_t mext[RED_MAXD], mx[RED_MAXD], mz[RED_MAXD];
+    FastDiv next[EIN_MAXO];
+    uint32_t ny[EIN_MAXO], nz[EIN_MAXO];
+    uint32_t sext[EIN_MAXS], sx[EIN_MAXS], sy[EIN_MAXS];
+    uint32_t M, N, K;
+    double alpha;
+    int accumulate;
+};
+
 // Adjoint of the last isometry product of one K slice, fused with the
 // adjoint of that isometry (one pass over the operand adjoint X):
 //   out[o, j, l]    = sum_{c, s} U[l, s, c] X[o, j, c, s]
@@ -227,6 +265,15 @@ bool launch_lastprod_adjoint(const LastProdParams &p, const double *X, const dou
                              double *out, double *Ubar, double *partial, hipStream_t s);
 void launch_einsum(EinsumParams p, const double *X, const double *Y, double *out, double *partial,
                    size_t partial_cap, hipStream_t s);
+// RedParams contraction; false (nothing launched) when the outputs exceed
+// 4096, the LDS staging exceeds 64 KB or the partial buffer cannot hold one
+// chunk per output
+bool launch_red(RedParams p, const double *X, const double *Y, double *out, double *partial, size_t partial_cap,
+                hipStream_t s);
+// XmvParams contraction (X gathered into xc, capacity xc_cap doubles); false
+// (nothing launched) when K > 100, M > 256 or xc is too small
+bool launch_xmv(const XmvParams &p, const double *X, const double *Y, double *out, double *xc, size_t xc_cap,
+                hipStream_t s);
 void launch_eigh_adjoint(const double *V, const double *lam, const double *Ubar, int n, int k, double *Ebar,
                          hipStream_t s);
 void launch_diag_set(double *T, const int D[4], const uint32_t diag_st[4], double value, hipStream_t s);

@@ -14,6 +14,8 @@
 // * seed and final contraction with dT^(0)/d(beta, h).
 #include "hotrg_internal.h"
 
+#include <algorithm>
+
 namespace hotrg {
 
 namespace {
@@ -106,6 +108,244 @@ void launch_einsum(EinsumParams p, const double *X, const double *Y, double *out
     if (gx > 65535) gx = 65535;
     einsum_kernel<<<dim3(gx, nch), kT, 0, s>>>(p, X, Y, out, partial);
     if (nch > 1) einsum_reduce_kernel<<<gx, kT, 0, s>>>(p, partial, out);
+}
+
+// ---------------------------------------------------------------------------
+// Outer-product reduction (see RedParams): the contractions whose outputs are
+// few and whose sums are long (the isometry adjoints, D^2 k outputs over D^6
+// or D^7 terms).  Workgroup c walks the summed range [c chunk, (c+1) chunk)
+// in blocks of RED_KB indices: the block's rows of X (RED_KB x Mo) and of Y
+// (RED_KB x No) are staged in LDS with coalesced loads (the operand's
+// contiguous index fastest), then each thread adds the block's terms of its
+// outputs in k order; the workgroup's partial sums go to `partial`, which
+// red_finish_kernel adds in chunk order (deterministic).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int RED_KB = 32;
+constexpr int RED_MAXO = 16;  // outputs per thread: Mo No <= 16 * 256
+}  // namespace
+
+__global__ void __launch_bounds__(kT) red_kernel(RedParams p, const double *__restrict__ X,
+                                                 const double *__restrict__ Y, double *__restrict__ partial) {
+    extern __shared__ __align__(16) double rsm[];
+    const uint32_t Mo = p.mo.d, No = p.no.d, nout = Mo * No;
+    double *Xs = rsm;                    // [RED_KB][Mo]
+    double *Ys = Xs + RED_KB * Mo;       // [RED_KB][No]
+    uint32_t *xk = (uint32_t *)(Ys + RED_KB * No);
+    uint32_t *yk = xk + RED_KB;
+    uint32_t *xmo = yk + RED_KB;         // [Mo]
+    uint32_t *yno = xmo + Mo;            // [No]
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < Mo; i += blockDim.x) {
+        uint32_t r = i, o = 0;
+        for (int d = p.ndm - 1; d >= 0; --d) {
+            o += (r % p.mext[d]) * p.mx[d];
+            r /= p.mext[d];
+        }
+        xmo[i] = o;
+    }
+    for (uint32_t i = tid; i < No; i += blockDim.x) {
+        uint32_t r = i, o = 0;
+        for (int d = p.ndn - 1; d >= 0; --d) {
+            o += (r % p.next[d]) * p.ny[d];
+            r /= p.next[d];
+        }
+        yno[i] = o;
+    }
+    double acc[RED_MAXO];
+#pragma unroll
+    for (int j = 0; j < RED_MAXO; ++j) acc[j] = 0.0;
+    const uint32_t k0 = blockIdx.x * p.chunk;
+    const uint32_t k1 = min(p.S, k0 + p.chunk);
+    for (uint32_t kb0 = k0; kb0 < k1; kb0 += RED_KB) {
+        const uint32_t nk = min((uint32_t)RED_KB, k1 - kb0);
+        __syncthreads();  // previous block consumed (and the offset tables written)
+        if (tid < nk) {
+            uint32_t r = kb0 + tid, xo = 0, yo = 0;
+            for (int d = p.nds - 1; d >= 0; --d) {
+                const uint32_t q = fast_div(r, p.sext[d]);
+                const uint32_t c = r - q * p.sext[d].d;
+                xo += c * p.sx[d];
+                yo += c * p.sy[d];
+                r = q;
+            }
+            xk[tid] = xo;
+            yk[tid] = yo;
+        }
+        __syncthreads();
+        for (uint32_t e = tid; e < RED_KB * Mo; e += blockDim.x) {
+            uint32_t kk, m;
+            if (p.xmfast) {
+                kk = fast_div(e, p.mo);
+                m = e - kk * Mo;
+            } else {
+                m = e / RED_KB;
+                kk = e % RED_KB;
+            }
+            if (kk < nk) Xs[kk * Mo + m] = X[xk[kk] + xmo[m]];
+        }
+        for (uint32_t e = tid; e < RED_KB * No; e += blockDim.x) {
+            uint32_t kk, n;
+            if (p.ynfast) {
+                kk = fast_div(e, p.no);
+                n = e - kk * No;
+            } else {
+                n = e / RED_KB;
+                kk = e % RED_KB;
+            }
+            if (kk < nk) Ys[kk * No + n] = Y[yk[kk] + yno[n]];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RED_MAXO; ++j) {
+            const uint32_t e = tid + j * blockDim.x;
+            if (e >= nout) break;
+            const uint32_t m = fast_div(e, p.no), n = e - m * No;
+            double a = acc[j];
+            for (uint32_t kk = 0; kk < nk; ++kk) a = fma(Xs[kk * Mo + m], Ys[kk * No + n], a);
+            acc[j] = a;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < RED_MAXO; ++j) {
+        const uint32_t e = tid + j * blockDim.x;
+        if (e < nout) partial[(size_t)blockIdx.x * nout + e] = acc[j];
+    }
+}
+
+__global__ void __launch_bounds__(kT) red_finish_kernel(RedParams p, const double *__restrict__ partial,
+                                                        double *__restrict__ out) {
+    const uint32_t Mo = p.mo.d, No = p.no.d, nout = Mo * No;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nout; e += gridDim.x * blockDim.x) {
+        const uint32_t m = fast_div(e, p.no), n = e - m * No;
+        uint32_t z = 0, r = m;
+        for (int d = p.ndm - 1; d >= 0; --d) {
+            z += (r % p.mext[d]) * p.mz[d];
+            r /= p.mext[d];
+        }
+        r = n;
+        for (int d = p.ndn - 1; d >= 0; --d) {
+            z += (r % p.next[d]) * p.nz[d];
+            r /= p.next[d];
+        }
+        double a = 0.0;
+        for (uint32_t c = 0; c < p.nchunks; ++c) a += partial[(size_t)c * nout + e];
+        const double v = p.alpha * a;
+        out[z] = p.accumulate ? out[z] + v : v;
+    }
+}
+
+size_t red_lds_bytes(const RedParams &p) {
+    return (size_t)RED_KB * (p.mo.d + p.no.d) * sizeof(double) + (size_t)(2 * RED_KB + p.mo.d + p.no.d) * 4;
+}
+
+bool launch_red(RedParams p, const double *X, const double *Y, double *out, double *partial, size_t partial_cap,
+                hipStream_t s) {
+    const size_t nout = (size_t)p.mo.d * p.no.d;
+    if (nout == 0 || nout > (size_t)RED_MAXO * kT || p.S == 0 || red_lds_bytes(p) > 64 * 1024) return false;
+    size_t nch = std::min<size_t>((p.S + 1023) / 1024, 2048);
+    nch = std::min(nch, partial_cap / nout);
+    if (nch < 1) return false;
+    uint32_t chunk = (uint32_t)((p.S + nch - 1) / nch);
+    chunk = (chunk + RED_KB - 1) / RED_KB * RED_KB;
+    p.chunk = chunk;
+    p.nchunks = (p.S + chunk - 1) / chunk;
+    red_kernel<<<p.nchunks, kT, red_lds_bytes(p), s>>>(p, X, Y, partial);
+    red_finish_kernel<<<(uint32_t)((nout + kT - 1) / kT), kT, 0, s>>>(p, partial, out);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Small-matrix products over many strided columns (see XmvParams): the
+// adjoints of the isometry products and of the Grams, where a small matrix
+// X (M x K, K <= 100) multiplies D^6..D^8 strided columns of Y.  One thread
+// per column n keeps the column's K values in registers; X is first gathered
+// into a dense M x KMAX array (zero past K) so that the product reads it
+// through wave-uniform addresses (scalar loads).
+// ---------------------------------------------------------------------------
+__global__ void xmv_gather_kernel(XmvParams p, const double *__restrict__ X, double *__restrict__ Xc, int kmax) {
+    const uint32_t M = p.M;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < M * (uint32_t)kmax; e += gridDim.x * blockDim.x) {
+        const uint32_t m = e / (uint32_t)kmax, k = e - m * (uint32_t)kmax;
+        double v = 0.0;
+        if (k < p.K) {
+            uint32_t o = 0, r = m;
+            for (int d = p.ndm - 1; d >= 0; --d) {
+                o += (r % p.mext[d]) * p.mx[d];
+                r /= p.mext[d];
+            }
+            r = k;
+            for (int d = p.nds - 1; d >= 0; --d) {
+                o += (r % p.sext[d]) * p.sx[d];
+                r /= p.sext[d];
+            }
+            v = X[o];
+        }
+        Xc[e] = v;
+    }
+}
+
+template <int KMAX>
+__global__ void __launch_bounds__(kT) xmv_kernel(XmvParams p, const double *__restrict__ Xc,
+                                                 const double *__restrict__ Y, double *__restrict__ out) {
+    __shared__ uint32_t yk[KMAX];
+    __shared__ uint32_t zmo[XMV_MAXM];
+    for (uint32_t k = threadIdx.x; k < KMAX; k += blockDim.x) {
+        uint32_t o = 0, r = k;
+        if (k < p.K)
+            for (int d = p.nds - 1; d >= 0; --d) {
+                o += (r % p.sext[d]) * p.sy[d];
+                r /= p.sext[d];
+            }
+        yk[k] = o;
+    }
+    for (uint32_t m = threadIdx.x; m < p.M; m += blockDim.x) {
+        uint32_t o = 0, r = m;
+        for (int d = p.ndm - 1; d >= 0; --d) {
+            o += (r % p.mext[d]) * p.mz[d];
+            r /= p.mext[d];
+        }
+        zmo[m] = o;
+    }
+    __syncthreads();
+    for (uint32_t n = blockIdx.x * blockDim.x + threadIdx.x; n < p.N; n += gridDim.x * blockDim.x) {
+        uint32_t rem = n, yb = 0, zb = 0;
+        for (int d = p.ndn - 1; d >= 0; --d) {
+            const uint32_t q = fast_div(rem, p.next[d]);
+            const uint32_t c = rem - q * p.next[d].d;
+            yb += c * p.ny[d];
+            zb += c * p.nz[d];
+            rem = q;
+        }
+        double y[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) y[k] = Y[yb + yk[k]];  // (k >= K: offset 0, met by a zero of Xc)
+        for (uint32_t m = 0; m < p.M; ++m) {
+            const double *xm = Xc + (size_t)m * KMAX;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) acc = fma(xm[k], y[k], acc);
+            double *o = out + zb + zmo[m];
+            const double v = p.alpha * acc;
+            *o = p.accumulate ? *o + v : v;
+        }
+    }
+}
+
+bool launch_xmv(const XmvParams &p, const double *X, const double *Y, double *out, double *xc, size_t xc_cap,
+                hipStream_t s) {
+    int kmax = p.K <= 16 ? 16 : (p.K <= 36 ? 36 : (p.K <= 64 ? 64 : (p.K <= 100 ? 100 : 0)));
+    if (kmax == 0 || p.M == 0 || p.M > XMV_MAXM || p.N == 0 || (size_t)p.M * kmax > xc_cap) return false;
+    const uint32_t ng = (uint32_t)std::min<size_t>(((size_t)p.M * kmax + kT - 1) / kT, 1024);
+    xmv_gather_kernel<<<ng, kT, 0, s>>>(p, X, xc, kmax);
+    const uint32_t g = (uint32_t)std::min<size_t>(((size_t)p.N + kT - 1) / kT, 65535);
+    switch (kmax) {
+        case 16: xmv_kernel<16><<<g, kT, 0, s>>>(p, xc, Y, out); break;
+        case 36: xmv_kernel<36><<<g, kT, 0, s>>>(p, xc, Y, out); break;
+        case 64: xmv_kernel<64><<<g, kT, 0, s>>>(p, xc, Y, out); break;
+        default: xmv_kernel<100><<<g, kT, 0, s>>>(p, xc, Y, out); break;
+    }
+    return true;
 }
 
 // ---------------------------------------------------------------------------
