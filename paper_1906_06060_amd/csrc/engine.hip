@@ -1723,6 +1723,13 @@ int run_lastprod(hotrg_ctx *c, const LastProdParams &p, const double *X, uint64_
     if (p.n_o1 == 0 || p.n_o2 == 0 || p.NJ == 0 || xmax >= xa || omax >= oa || umax >= ua || xmax >= (1ull << 32) ||
         omax >= (1ull << 32))
         return HOTRG_OK;
+    if (p.cls) {
+        // class-block source: natural offsets split as (o1 x_o1 + c xc) + (o2 x_o2 + j xj + s xs),
+        // rows (multiples of ks) and K indices below ks
+        const uint64_t ks = p.ks.d;
+        const uint64_t kmax = (uint64_t)(p.n_o2 - 1) * p.x_o2 + (uint64_t)(p.NJ - 1) * p.xj + (uint64_t)(p.N - 1) * p.xs;
+        if (ks == 0 || p.x_o1 % ks != 0 || p.xc % ks != 0 || kmax >= ks) return HOTRG_OK;
+    }
     double *part;
     TRY(bw_buf(c, BW_PART, ((size_t)p.n_o1 * p.n_o2 + 64) * p.L * p.N * p.N, &part));
     if (!launch_lastprod_adjoint(p, X, Y, U, out, Ubar, part, c->stream)) return HOTRG_OK;
@@ -2296,11 +2303,9 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                     launch_gemm_bf16x3_multi(ga, n, c->stream, tail);
                     launch_gemm_bf16x3_multi(gb, n, c->stream, tail);
                 }
-                // A_bar's columns follow the rows of B^T (ktabq order), B_bar's those of A^T
-                launch_z2_unscatter(zAo[0], zAo[1], zKc[0], zKc[1], c->rtab, c->kmapq, zs, 0u, (uint32_t)Ks,
-                                    (uint32_t)M, Abar, c->stream);
-                launch_z2_unscatter(zBo[0], zBo[1], zKc[0], zKc[1], c->rtab, c->ktab, zs, 0u, (uint32_t)Ks,
-                                    (uint32_t)M, Bbar, c->stream);
+                // (A_bar and B_bar stay in class blocks: the fused last-product
+                // adjoints read them through the tables, and the natural layout
+                // is written only for the generic fallback below)
             } else if (mixed) {
                 launch_gemm_bf16x3(Ch, Cl, BTh, BTl, Abar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream, tail);
                 launch_gemm_bf16x3(CTh, CTl, ATh, ATl, Bbar, (int)M, 1, (int)Ks, (int)ldM, Ks, 0, c->stream, tail);
@@ -2329,8 +2334,22 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 lp.uc = 1;
                 lp.L = kc;
                 lp.N = Dc;
+                if (z2) {  // A_bar's columns follow the rows of B^T (the ktabq order, listed densely by kmapq)
+                    lp.cls = 1;
+                    lp.blk[0] = zAo[0];
+                    lp.blk[1] = zAo[1];
+                    lp.ldb[0] = zKc[0];
+                    lp.ldb[1] = zKc[1];
+                    lp.rtab = c->rtab;
+                    lp.ktab = c->kmapq;
+                    lp.zs = zs;
+                    lp.ks = make_fastdiv((uint32_t)Ks);
+                }
                 TRY(run_lastprod(c, lp, Abar, M * Ks, Y2, Uc, usz[2], Yb2, c->cap, Ubar[2], &fusedA));
             }
+            if (!fusedA && z2)
+                launch_z2_unscatter(zAo[0], zAo[1], zKc[0], zKc[1], c->rtab, c->kmapq, zs, 0u, (uint32_t)Ks,
+                                    (uint32_t)M, Abar, c->stream);
             if (!fusedA) {   // Yb2[a,b,mu1,b1',c1',a2,b2,c1] = sum_{c,c2} Uc[(c1,c2),c] A_bar[(a,b,mu1,c),(b1',c1',a2,b2,c2)]
                 EP e;
                 e.o(ka, r0 * Ks, 0, y2s[0]);
@@ -2431,8 +2450,22 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
                 lp.uc = 1;
                 lp.L = kc;
                 lp.N = Dc;
+                if (z2) {  // B_bar's columns follow the rows of A^T (the dense order of ktab)
+                    lp.cls = 1;
+                    lp.blk[0] = zBo[0];
+                    lp.blk[1] = zBo[1];
+                    lp.ldb[0] = zKc[0];
+                    lp.ldb[1] = zKc[1];
+                    lp.rtab = c->rtab;
+                    lp.ktab = c->ktab;
+                    lp.zs = zs;
+                    lp.ks = make_fastdiv((uint32_t)Ks);
+                }
                 TRY(run_lastprod(c, lp, Bbar, M * Ks, Z2, Uc, usz[2], Yb2, c->cap, Ubar[2], &fusedB));
             }
+            if (!fusedB && z2)
+                launch_z2_unscatter(zBo[0], zBo[1], zKc[0], zKc[1], c->rtab, c->ktab, zs, 0u, (uint32_t)Ks,
+                                    (uint32_t)M, Bbar, c->stream);
             if (!fusedB) {   // Zb2[a',b',mu2',b1',a2,b2,c2,c2'] = sum_{c',c1'} Uc[(c1',c2'),c'] B_bar[(a',b',mu2',c'),(b1',c1',a2,b2,c2)]
                 EP e;
                 e.o(ka, r0 * Ks, 0, z2s[0]);

@@ -181,6 +181,16 @@ struct LastProdParams {
     uint32_t out_o1, out_o2, oj, ol;
     uint32_t ul, us, uc;
     int L, N;
+    // cls: X is given in Z2 class blocks instead (reverse pass, block form):
+    // the natural offset o of an X entry splits into the row r = o / ks and
+    // the K index k = o - r ks; the entry is blk[b][pos(r) ldb[b] + pos(k)]
+    // (b = class of k in ktab) when the parity of r (rtab) is b ^ zs, else 0
+    int cls;
+    const double *blk[2];
+    uint32_t ldb[2];
+    const uint32_t *rtab, *ktab;
+    uint32_t zs;
+    FastDiv ks;
 };
 
 constexpr int PERM_MAXD = 8;

@@ -6,7 +6,12 @@
 //   thread) and optionally split into chunks whose partial sums are added in a
 //   fixed order (deterministic).  Every adjoint of an isometry product, of an
 //   isometry itself, of the environment combination and of the Grams is one
-//   such contraction.
+//   such contraction; the host sends the two shapes that dominate the reverse
+//   pass to dedicated kernels instead (red_kernel: few outputs, long sums;
+//   xmv_kernel: a small matrix times many strided columns).
+// * lastprod_adjoint_kernel: the adjoint of the last isometry product of a K
+//   slice fused with that isometry's adjoint, reading the operand adjoint in
+//   the natural layout or in Z2 class blocks.
 // * eigh_adjoint_kernel: E_bar = sym(V_perp (F o (V_perp^T U_bar)) U^T) with
 //   F[j, i] = 1 / (lam_i - lam_j) for kept i and discarded j -- the derivative
 //   of the kept eigenvectors restricted to kept x discarded pairs (rotations
@@ -379,6 +384,11 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
     double *sU = lp_sm;                       // PAIRS: [l][c][s], else [l][s][c]   N * N * L
     double *sX = sU + N * N * L;              // [jj][c][s] JT * L * N
     double *sY = sX + LP_JT * L * N;          // [jj][l]    JT * N
+    // class-block source: table entries of the tile's rows (one per c) and K
+    // indices (one per jj, s), the natural offset being r ks + k with
+    // r = (o1 x_o1 + c xc) / ks and k = o2 x_o2 + j xj + s xs (host-checked)
+    uint32_t *sRt = (uint32_t *)(sY + LP_JT * N);  // [c]      L
+    uint32_t *sKt = sRt + LP_MAXL;                   // [jj][s]  JT * N
     const int tid = threadIdx.x;
     const int nU = N * N * L;
     for (int u = tid; u < nU; u += blockDim.x) {
@@ -397,12 +407,32 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
     for (int q = 0; q < 4 * LP_PB; ++q) pacc[q] = 0.0;
     constexpr int NH = PAIRS ? N / 2 : 1;
     const int nblk = PAIRS ? NH * (L * N / 2) : 0;  // 2 x 2 blocks of the isometry adjoint
+    if (p.cls)
+        for (int c = tid; c < L; c += blockDim.x) sRt[c] = p.rtab[(o1 * p.x_o1 + c * p.xc) / p.ks.d];
     for (uint32_t j0 = 0; j0 < p.NJ; j0 += LP_JT) {
         __syncthreads();  // previous tile consumed (and sU staged on the first pass)
+        if (p.cls) {
+            for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
+                const int s = idx % N, jj = idx / N;
+                const uint32_t j = j0 + jj;
+                sKt[idx] = j < p.NJ ? p.ktab[o2 * p.x_o2 + j * p.xj + s * p.xs] : 0u;
+            }
+            __syncthreads();
+        }
         for (int idx = tid; idx < LP_JT * L * N; idx += blockDim.x) {
             const int s = idx % N, c = (idx / N) % L, jj = idx / (N * L);
             const uint32_t j = j0 + jj;
-            sX[idx] = j < p.NJ ? X[xo + j * p.xj + c * p.xc + s * p.xs] : 0.0;
+            double v = 0.0;
+            if (j < p.NJ) {
+                if (p.cls) {
+                    const uint32_t kt = sKt[jj * N + s], rt = sRt[c], b = kt >> 31;
+                    if ((rt >> 31) == (b ^ p.zs))
+                        v = p.blk[b][(size_t)(rt & ~Z2_PAR) * p.ldb[b] + (kt & ~Z2_PAR)];
+                } else {
+                    v = X[xo + j * p.xj + c * p.xc + s * p.xs];
+                }
+            }
+            sX[idx] = v;
         }
         for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
             const int l = idx % N, jj = idx / N;
@@ -532,7 +562,8 @@ template <int N>
 void launch_lastprod_n(const LastProdParams &p, const double *X, const double *Y, const double *U, double *out,
                        double *Ubar, double *partial, hipStream_t s) {
     const uint32_t nb = p.n_o1 * p.n_o2;
-    const size_t lds = sizeof(double) * ((size_t)N * N * p.L + (size_t)LP_JT * p.L * N + (size_t)LP_JT * N);
+    const size_t lds = sizeof(double) * ((size_t)N * N * p.L + (size_t)LP_JT * p.L * N + (size_t)LP_JT * N) +
+                       sizeof(uint32_t) * ((size_t)LP_MAXL + (size_t)LP_JT * N);
     lastprod_adjoint_kernel<N><<<nb, kT, lds, s>>>(p, X, Y, U, out, partial);
     const int nU = N * N * p.L;
     double *part2 = partial + (size_t)nb * nU;  // LP_G rows after the per-workgroup ones
