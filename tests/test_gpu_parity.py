@@ -424,3 +424,15 @@ def test_contraction_sampled_d10_fp64(H):
     # at D = 8 above and on whole tensors at small dims.)
     w = _sampled_parity(H, 10, 2, H.FP64, False, 32, 1e-13, seed=61, z2=True)
     print(f"fp64 D=10 (Z2 blocks): worst scaled error {w:.3e}")
+
+
+# ----------------- D = 12 sampled contraction (opt-in) ----
+@pytest.mark.skipif(os.environ.get("HOTRG_DCUT12") != "1",
+                    reason="D = 12: about 30 GB of host tensors and row vectors and a 45 s step; "
+                           "run with HOTRG_DCUT12=1")
+def test_contraction_sampled_d12_bf16x3(H):
+    # the Dcut = 12 configuration's contraction: bf16x3, T | S_m | S_e rows, K
+    # slices that also fix b1' (a two-index slice would exceed 2^31 elements
+    # per tensor), Z2 block form; 16 sampled rows x 16 columns of each tensor
+    w = _sampled_parity(H, 12, 1, H.BF16X3, True, 16, 6e-5, seed=81, z2=True)
+    print(f"bf16x3 D=12 (Z2 blocks, b1' slices): worst scaled error over 16 x 16 x 3 entries {w:.3e}")

@@ -38,7 +38,11 @@ def test_kernel_stats_rejects_unknown_index(H):
     import ctypes as C
     with H.Context(0.1497, 0.0, 2) as ctx:
         ms, fl, ln = C.c_double(), C.c_double(), C.c_longlong()
-        rc = H._lib.hotrg_kernel_stats(ctx._h, 4, C.byref(ms), C.byref(ln), C.byref(fl))
-        assert rc == -1
+        for k in (-1, 6):
+            rc = H._lib.hotrg_kernel_stats(ctx._h, k, C.byref(ms), C.byref(ln), C.byref(fl))
+            assert rc == -1
+        for k in (4, 5):  # tile-scatter launches, reverse steps in the block form
+            assert H._lib.hotrg_kernel_stats(ctx._h, k, C.byref(ms), C.byref(ln), C.byref(fl)) == 0
+            assert ln.value == 0 and ms.value == 0.0
         ctx.reset_stats()
         assert ctx.phase_stats()["steps"] == 0
