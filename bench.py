@@ -156,6 +156,8 @@ def precision_study(a):
             t0 = time.perf_counter()
             runs[name] = H.flow(beta, a.h, a.dcut, a.precision_study, precision=prec)
             runs[name + "_s"] = time.perf_counter() - t0
+            print(f"[precision-study] beta={beta} {name}: {a.precision_study} steps in "
+                  f"{runs[name + '_s']:.1f} s", file=sys.stderr, flush=True)
         rows = []
         for f, m in zip(runs["fp64"], runs["bf16x3"]):
             rows.append({"n": f["n"], "lnz_fp64": f["lnz_per_site"],
