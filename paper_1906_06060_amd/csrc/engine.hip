@@ -939,7 +939,9 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
         z2_brows = Nmax;
         uint64_t need = 0, offs[2][2];
         for (int b = 0; b < 2; ++b) {
-            zl.ldk[b] = mixed ? ((uint64_t)zl.Kc[b] + 63) / 64 * 64 : zl.Kc[b];
+            // bf16: whole packed k blocks; FP64: an even row length, so that
+            // every row is 16-byte aligned for the DGEMM's vector loads
+            zl.ldk[b] = mixed ? ((uint64_t)zl.Kc[b] + 63) / 64 * 64 : ((uint64_t)zl.Kc[b] + 1) / 2 * 2;
             const uint64_t ar = mixed ? packed_rows(Amax) : Amax, br = mixed ? packed_rows(Nmax) : Nmax;
             offs[b][0] = need;
             need += ar * zl.ldk[b];
@@ -1189,7 +1191,8 @@ int contract(hotrg_ctx *c, int mu, const int tv[3], const int k[3]) {
                     if (mixed)
                         xg[nx++] = X3Gemm{zAh[b], zAl[b], zBh[b], zBl[b], Cg, (int)R, 1, (int)N, (int)zl.ldk[b], N, acc};
                     else
-                        launch_gemm_f64(zA[b], zB[b], Cg, (int)R, (int)N, (int)Kb, Kb, Kb, N, acc, c->stream);
+                        launch_gemm_f64(zA[b], zB[b], Cg, (int)R, (int)N, (int)Kb, zl.ldk[b], zl.ldk[b], N, acc,
+                                        c->stream);
                     fl += 2.0 * (double)R * (double)N * (double)Kb;
                 }
                 if (mixed && nx > 0) launch_gemm_bf16x3_multi(xg, nx, c->stream, tail);
@@ -2035,7 +2038,7 @@ int backward_step(hotrg_ctx *c, const hotrg_ctx::Checkpoint &cp, const double *T
         // class buffers: C_bar_g (and transposes) packed for the bf16x3 GEMMs,
         // transposed class operands (rows K_b, row length zld[g]), GEMM outputs
         const uint32_t Nmax = std::max(zN[0], zN[1]);
-        for (int g = 0; g < 2; ++g) zld[g] = mixed ? ((uint64_t)zN[g] + 63) / 64 * 64 : zN[g];
+        for (int g = 0; g < 2; ++g) zld[g] = mixed ? ((uint64_t)zN[g] + 63) / 64 * 64 : ((uint64_t)zN[g] + 1) / 2 * 2;
         const uint64_t ldmax = std::max<uint64_t>(std::max(zld[0], zld[1]), 1);
         if ((uint64_t)Nmax * ldmax >= (1ull << 31) || (uint64_t)std::max(zKc[0], zKc[1]) * ldmax >= (1ull << 31))
             return set_err(HOTRG_ENOMEM, "reverse pass: class operand exceeds 2^31 elements");

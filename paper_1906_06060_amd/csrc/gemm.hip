@@ -4,10 +4,10 @@
 //
 // The O(D^15) contraction of Sec. 2 (cost paragraph) is exactly this
 // product with M = N = D^4 and K = D^7 (taken in K slices):
-//   * gemm_f64:    FP64 on the vector FMA units (on gfx950 they issue at
-//                  about twice the rate of v_mfma_f64_16x16x4 measured in
+//   * gemm_f64:    FP64 on the vector FMA units (under load they sustain
+//                  about 1.3x the rate of v_mfma_f64_16x16x4 measured in
 //                  register-only loops), 128 x 128 tile, 8 x 8 outputs per
-//                  thread, operands staged k-major in LDS;
+//                  thread, operands staged k-major in a two-slot LDS ring;
 //   * gemm_bf16x3: v_mfma_f32_32x32x16_bf16 on hi/lo splits (3 products),
 //                  256 x 256 tile, 8 waves of 128 x 64 (two per SIMD), 32 k
 //                  per LDS stage loaded directly into a two-slot LDS ring
@@ -52,24 +52,32 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int &
 
 // ------------------------------------------------------------------ FP64 ---
 namespace f64 {
-constexpr int BM = 128, BN = 128, BK = 16, PAD = 4, NT = 256;
+constexpr int BM = 128, BN = 128, BK = 8, PAD = 4, NT = 256;
+constexpr int PER = BK / 2;  // k values each thread stages per operand and stage
 
 // Register-blocked DGEMM: a 16 x 16 thread grid, each thread owns the row
 // pairs 2 ty + 32 i + {0, 1} and the column pairs 2 tx + 32 j + {0, 1}
-// (i, j < 4); operands staged k-major in LDS, so every operand pair is one
-// 16-byte LDS read (a wave reads 4 broadcast A pairs and 16 consecutive B
-// pairs per k) and C is written in 16-byte pairs.
+// (i, j < 4); operands staged k-major in a two-slot LDS ring, so every
+// operand pair is one 16-byte LDS read (a wave reads 4 broadcast A pairs and
+// 16 consecutive B pairs per k) and there is one barrier per stage: stage
+// s + 1 is fetched into registers while stage s is multiplied, then written
+// to the other slot.  Thread t stages k values [PER (t & 1), PER (t & 1) +
+// PER) of tile row t / 2; with VEC (both leading dimensions even, operands
+// 16-byte aligned) those are 16-byte loads, which measured 11-13% faster
+// than 8-byte ones on the contraction shapes.  The sum over k runs in
+// ascending order in every variant.
+template <bool VEC>
 __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__ A, const double *__restrict__ B,
                                                        double *__restrict__ C, int M, int N, int K, size_t lda,
                                                        size_t ldb, size_t ldc, int accumulate, int tiles_m,
                                                        int tiles_n) {
-    __shared__ __align__(16) double As[BK][BM + PAD];
-    __shared__ __align__(16) double Bs[BK][BN + PAD];
+    __shared__ __align__(16) double As[2][BK][BM + PAD];
+    __shared__ __align__(16) double Bs[2][BK][BN + PAD];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     int tm, tn;
     tile_of(blockIdx.x, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
-    const int lr = tid >> 1, kp = (tid & 1) * 8;
+    const int lr = tid >> 1, kp = (tid & 1) * PER;
     const bool arow = (m0 + lr) < M, brow = (n0 + lr) < N;
     const double *Ap = A + (size_t)(arow ? m0 + lr : 0) * lda;
     const double *Bp = B + (size_t)(brow ? n0 + lr : 0) * ldb;
@@ -78,31 +86,49 @@ __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__
     for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
-    double ra[8], rb[8];
+    double ra[PER], rb[PER];
     auto gload = [&](int k0) {
+        const int kb = k0 + kp;
+        if (VEC && kb + PER <= K) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            int k = k0 + kp + j;
-            ra[j] = (arow && k < K) ? Ap[k] : 0.0;
-            rb[j] = (brow && k < K) ? Bp[k] : 0.0;
+            for (int j = 0; j < PER; j += 2) {
+                const double2 va = arow ? *(const double2 *)(Ap + kb + j) : double2{0.0, 0.0};
+                const double2 vb = brow ? *(const double2 *)(Bp + kb + j) : double2{0.0, 0.0};
+                ra[j] = va.x;
+                ra[j + 1] = va.y;
+                rb[j] = vb.x;
+                rb[j + 1] = vb.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int k = kb + j;
+                ra[j] = (arow && k < K) ? Ap[k] : 0.0;
+                rb[j] = (brow && k < K) ? Bp[k] : 0.0;
+            }
         }
     };
-    gload(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    auto lstore = [&](int slot) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            As[kp + j][lr] = ra[j];
-            Bs[kp + j][lr] = rb[j];
+        for (int j = 0; j < PER; ++j) {
+            As[slot][kp + j][lr] = ra[j];
+            Bs[slot][kp + j][lr] = rb[j];
         }
-        __syncthreads();
-        if (k0 + BK < K) gload(k0 + BK);
-#pragma unroll 4
+    };
+    const int ns = (K + BK - 1) / BK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < ns) gload((s + 1) * BK);
+#pragma unroll 2
         for (int kk = 0; kk < BK; ++kk) {
             double a[8], b[8];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const double2 va = *(const double2 *)&As[kk][2 * ty + 32 * i];
-                const double2 vb = *(const double2 *)&Bs[kk][2 * tx + 32 * i];
+                const double2 va = *(const double2 *)&As[cur][kk][2 * ty + 32 * i];
+                const double2 vb = *(const double2 *)&Bs[cur][kk][2 * tx + 32 * i];
                 a[2 * i] = va.x;
                 a[2 * i + 1] = va.y;
                 b[2 * i] = vb.x;
@@ -113,6 +139,9 @@ __global__ void __launch_bounds__(NT) gemm_f64_kernel(const double *__restrict__
 #pragma unroll
                 for (int j = 0; j < 8; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
         }
+        // the other slot was last read in stage s - 1, before the barrier
+        // that ended it; the barrier below publishes it for stage s + 1
+        if (s + 1 < ns) lstore(cur ^ 1);
         __syncthreads();
     }
 #pragma unroll
@@ -135,7 +164,12 @@ void launch_gemm_f64(const double *A, const double *B, double *C, int M, int N, 
                      size_t ldc, int accumulate, hipStream_t s) {
     if (M <= 0 || N <= 0) return;
     int tm = (M + f64::BM - 1) / f64::BM, tn = (N + f64::BN - 1) / f64::BN;
-    f64::gemm_f64_kernel<<<tm * tn, f64::NT, 0, s>>>(A, B, C, M, N, K, lda, ldb, ldc, accumulate, tm, tn);
+    const bool vec = lda % 2 == 0 && ldb % 2 == 0 && (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0;
+    if (vec)
+        f64::gemm_f64_kernel<true><<<tm * tn, f64::NT, 0, s>>>(A, B, C, M, N, K, lda, ldb, ldc, accumulate, tm, tn);
+    else
+        f64::gemm_f64_kernel<false><<<tm * tn, f64::NT, 0, s>>>(A, B, C, M, N, K, lda, ldb, ldc, accumulate, tm,
+                                                                tn);
 }
 
 // ---------------------------------------------------------------- bf16x3 ---
