@@ -356,16 +356,32 @@ bool launch_xmv(const XmvParams &p, const double *X, const double *Y, double *ou
 // ---------------------------------------------------------------------------
 // Fused adjoint of the last isometry product of a K slice (see
 // LastProdParams).  Workgroup (o1, o2) walks j in tiles of JT: the tile of X
-// (JT x L x N) and of Y (JT x N) is staged in LDS, the JT x N outputs are
-// written (sum over c, then s, in the order of the generic contraction), and
-// each thread keeps running sums of its isometry-adjoint entries; at the end
-// the workgroup stores them as one row of `partial`.
+// (JT x L N, row (j) by (c, s)) and of Y (JT x N) is staged in LDS, and both
+// products of the tile are small dense matrix products on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64):
+//   outputs    D[j, l]   = sum_cs X[j, cs] U[l, cs]   (16 j x 16 l blocks),
+//   isometry   E[l, cs] += sum_j Y[j, l] X[j, cs]      (16 l x 16 cs blocks,
+//              accumulated over the tiles in the matrix registers);
+// at the end the workgroup stores E as one row of `partial`.  The products
+// take a small part of the time; the kernel is bound by the gather of X
+// (through the class tables in the block form), which the element-wise form
+// of the same sums (three LDS operands per four FMAs) had hidden only in part.
+// MFMA operand layout (16 x 4 A, 4 x 16 B, 16 x 16 D): lane t
+// supplies A[t % 16][t / 16] and B[t / 16][t % 16], and holds D[4 i + t / 16]
+// [t % 16] in its register i.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int LP_JT = 32;
 constexpr int LP_MAXL = 16;
-constexpr int LP_UPT = 9;  // isometry-adjoint entries per thread: L N N <= 16 * 12 * 12 = 2304 = 256 * 9
-constexpr int LP_PB = 3;   // 2 x 2 entry blocks per thread with N even: 2304 / 4 = 576 <= 256 * 3
+constexpr int LP_UPT = 9;  // L N N <= 16 * 12 * 12 = 2304 = 256 * 9 isometry-adjoint entries
+constexpr int LP_MAXB = 3;  // 16-column blocks of E per wave: L N <= 192 = 12 blocks over 4 waves
+typedef double lp_dbl4 __attribute__((ext_vector_type(4)));
+
+// LDS row length of the X / U tiles: L N rounded up to whole 4-column MFMA
+// steps, plus one (an odd stride spreads the 16 rows of an operand read over
+// the banks); the padding columns hold zeros.  (Kept short: at 4 workgroups
+// per CU the usual grid of one slice, 1000 workgroups, runs in one round.)
+__host__ __device__ inline int lp_stride(int L, int N) { return (L * N + 3) / 4 * 4 + 1; }
 }  // namespace
 
 template <int N>
@@ -374,39 +390,37 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
                                                               const double *__restrict__ U,
                                                               double *__restrict__ out,
                                                               double *__restrict__ partial) {
-    // With N even every operand pair below is one aligned 16-byte LDS read:
-    // the outputs take (j, l pair) per thread with U staged [l][c][s], the
-    // isometry adjoint takes 2 l x 2 (c, s) entries per thread.  Every sum
-    // keeps the order of the one-entry-per-thread form (odd N).
-    constexpr bool PAIRS = N % 2 == 0;
+    static_assert(N <= 16, "one 16-wide block of l");
     extern __shared__ __align__(16) double lp_sm[];
-    const int L = p.L;
-    double *sU = lp_sm;                       // PAIRS: [l][c][s], else [l][s][c]   N * N * L
-    double *sX = sU + N * N * L;              // [jj][c][s] JT * L * N
-    double *sY = sX + LP_JT * L * N;          // [jj][l]    JT * N
+    const int L = p.L, LN = L * N;
+    const int SX = lp_stride(L, N);
+    const int NB = (LN + 15) / 16;     // 16-column blocks of E
+    const int KP = (LN + 3) / 4 * 4;   // k extent of the output products (< SX)
+    double *sU = lp_sm;                // [l][cs]  N * SX
+    double *sX = sU + N * SX;          // [jj][cs] JT * SX
+    double *sY = sX + LP_JT * SX;      // [jj][l]  JT * N
     // class-block source: table entries of the tile's rows (one per c) and K
     // indices (one per jj, s), the natural offset being r ks + k with
     // r = (o1 x_o1 + c xc) / ks and k = o2 x_o2 + j xj + s xs (host-checked)
     uint32_t *sRt = (uint32_t *)(sY + LP_JT * N);  // [c]      L
     uint32_t *sKt = sRt + LP_MAXL;                   // [jj][s]  JT * N
-    const int tid = threadIdx.x;
-    const int nU = N * N * L;
-    for (int u = tid; u < nU; u += blockDim.x) {
-        if (PAIRS) {
-            const int s = u % N, c = (u / N) % L, l = u / (L * N);
-            sU[u] = U[l * p.ul + s * p.us + c * p.uc];
-        } else {
-            const int c = u % L, s = (u / L) % N, l = u / (L * N);
-            sU[u] = U[l * p.ul + s * p.us + c * p.uc];
-        }
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nw = (int)blockDim.x >> 6;
+    for (int u = tid; u < (N + LP_JT) * SX; u += blockDim.x) lp_sm[u] = 0.0;
+    __syncthreads();
+    for (int u = tid; u < N * LN; u += blockDim.x) {
+        const int cs = u % LN, l = u / LN, c = cs / N, s = cs - c * N;
+        sU[l * SX + cs] = U[l * p.ul + s * p.us + c * p.uc];
     }
     const uint32_t o1 = blockIdx.x / p.n_o2, o2 = blockIdx.x % p.n_o2;
     const uint32_t xo = o1 * p.x_o1 + o2 * p.x_o2, oo = o1 * p.out_o1 + o2 * p.out_o2;
-    double pacc[4 * LP_PB];  // >= LP_UPT
+    lp_dbl4 eacc[LP_MAXB];
 #pragma unroll
-    for (int q = 0; q < 4 * LP_PB; ++q) pacc[q] = 0.0;
-    constexpr int NH = PAIRS ? N / 2 : 1;
-    const int nblk = PAIRS ? NH * (L * N / 2) : 0;  // 2 x 2 blocks of the isometry adjoint
+    for (int q = 0; q < LP_MAXB; ++q) eacc[q] = lp_dbl4{0.0, 0.0, 0.0, 0.0};
+    // operand rows of this lane: l = lr (clamped; lanes with lr >= N supply zeros)
+    const bool lok = lr < N;
+    const int lrc = lok ? lr : N - 1;
     if (p.cls)
         for (int c = tid; c < L; c += blockDim.x) sRt[c] = p.rtab[(o1 * p.x_o1 + c * p.xc) / p.ks.d];
     for (uint32_t j0 = 0; j0 < p.NJ; j0 += LP_JT) {
@@ -419,8 +433,8 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
             }
             __syncthreads();
         }
-        for (int idx = tid; idx < LP_JT * L * N; idx += blockDim.x) {
-            const int s = idx % N, c = (idx / N) % L, jj = idx / (N * L);
+        for (int idx = tid; idx < LP_JT * LN; idx += blockDim.x) {
+            const int cs = idx % LN, jj = idx / LN, c = cs / N, s = cs - c * N;
             const uint32_t j = j0 + jj;
             double v = 0.0;
             if (j < p.NJ) {
@@ -432,7 +446,7 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
                     v = X[xo + j * p.xj + c * p.xc + s * p.xs];
                 }
             }
-            sX[idx] = v;
+            sX[jj * SX + cs] = v;
         }
         for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
             const int l = idx % N, jj = idx / N;
@@ -440,95 +454,60 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
             sY[idx] = j < p.NJ ? Y[oo + j * p.oj + l * p.ol] : 0.0;
         }
         __syncthreads();
-        if (PAIRS) {
-            // outputs (j, l) and (j, l + 1): sum over c, then s
-            for (int idx = tid; idx < LP_JT * NH; idx += blockDim.x) {
-                const int l = 2 * (idx % NH), jj = idx / NH;
-                const uint32_t j = j0 + jj;
-                if (j >= p.NJ) continue;
-                const double *xr = sX + jj * L * N;
-                const double *u0 = sU + l * L * N, *u1 = u0 + L * N;
-                double a0 = 0.0, a1 = 0.0;
-                for (int c = 0; c < L; ++c)
-#pragma unroll
-                    for (int s = 0; s < N; s += 2) {
-                        const double2 x2 = *(const double2 *)(xr + c * N + s);
-                        const double2 v0 = *(const double2 *)(u0 + c * N + s);
-                        const double2 v1 = *(const double2 *)(u1 + c * N + s);
-                        a0 = fma(v0.x, x2.x, a0);
-                        a0 = fma(v0.y, x2.y, a0);
-                        a1 = fma(v1.x, x2.x, a1);
-                        a1 = fma(v1.y, x2.y, a1);
-                    }
-                out[oo + j * p.oj + l * p.ol] = a0;
-                out[oo + j * p.oj + (l + 1) * p.ol] = a1;
+        // outputs: one 16 j x 16 l block per wave (rows past NJ and columns
+        // past N are computed from zeros and not stored)
+        for (int jb = wave; jb < LP_JT / 16; jb += nw) {
+            // two independent accumulation chains (k steps alternate)
+            lp_dbl4 d = {0.0, 0.0, 0.0, 0.0}, d2 = {0.0, 0.0, 0.0, 0.0};
+            const double *xa = sX + (jb * 16 + lr) * SX + lk;
+            const double *ub = sU + lrc * SX + lk;
+            int k0 = 0;
+            for (; k0 + 8 <= KP; k0 += 8) {
+                const double a0 = xa[k0], b0 = ub[k0], a1 = xa[k0 + 4], b1 = ub[k0 + 4];
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, lok ? b0 : 0.0, d, 0, 0, 0);
+                d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, lok ? b1 : 0.0, d2, 0, 0, 0);
             }
-            // isometry adjoint: block b = (l pair, (c, s) pair), running sums over jj
+            if (k0 < KP) {
+                const double a0 = xa[k0], b0 = ub[k0];
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, lok ? b0 : 0.0, d, 0, 0, 0);
+            }
+            d += d2;
+            if (lok)
 #pragma unroll
-            for (int q = 0; q < LP_PB; ++q) {
-                const int b = tid + q * (int)blockDim.x;
-                if (b >= nblk) break;
-                const int l = 2 * (b % NH), cs = 2 * (b / NH);
-                double a00 = pacc[4 * q], a01 = pacc[4 * q + 1], a10 = pacc[4 * q + 2], a11 = pacc[4 * q + 3];
-#pragma unroll 4
-                for (int jj = 0; jj < LP_JT; ++jj) {
-                    const double2 y = *(const double2 *)(sY + jj * N + l);
-                    const double2 x = *(const double2 *)(sX + jj * L * N + cs);
-                    a00 = fma(y.x, x.x, a00);
-                    a01 = fma(y.x, x.y, a01);
-                    a10 = fma(y.y, x.x, a10);
-                    a11 = fma(y.y, x.y, a11);
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t j = j0 + jb * 16 + 4 * i + lk;
+                    if (j < p.NJ) out[oo + j * p.oj + lr * p.ol] = d[i];
                 }
-                pacc[4 * q] = a00;
-                pacc[4 * q + 1] = a01;
-                pacc[4 * q + 2] = a10;
-                pacc[4 * q + 3] = a11;
-            }
-        } else {
-            // outputs of the tile
-            for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
-                const int l = idx % N, jj = idx / N;
-                const uint32_t j = j0 + jj;
-                if (j >= p.NJ) continue;
-                const double *xr = sX + jj * L * N;
-                const double *ur = sU + l * N * L;
-                double acc = 0.0;
-                for (int c = 0; c < L; ++c)
+        }
+        // isometry adjoint: E blocks wave, wave + nw, ... (rows l, columns cs)
 #pragma unroll
-                    for (int s = 0; s < N; ++s) acc = fma(ur[s * L + c], xr[c * N + s], acc);
-                out[oo + j * p.oj + l * p.ol] = acc;
-            }
-            // isometry-adjoint running sums (padding rows of the tile are zero)
+        for (int q = 0; q < LP_MAXB; ++q) {
+            const int cb = wave + q * nw;
+            if (cb >= NB) break;
+            lp_dbl4 d = eacc[q];
+            const int cc = cb * 16 + lr;  // column cs of this lane (>= LN: zeros)
+            const int ccc = cc < LN ? cc : LN - 1;
 #pragma unroll
-            for (int q = 0; q < LP_UPT; ++q) {
-                const int u = tid + q * (int)blockDim.x;
-                if (u >= nU) break;
-                const int c = u % L, s = (u / L) % N, l = u / (L * N);
-                double a = pacc[q];
-#pragma unroll 4
-                for (int jj = 0; jj < LP_JT; ++jj) a = fma(sY[jj * N + l], sX[(jj * L + c) * N + s], a);
-                pacc[q] = a;
+            for (int k0 = 0; k0 < LP_JT; k0 += 4) {
+                const double ya = sY[(k0 + lk) * N + lrc];
+                const double xb = sX[(k0 + lk) * SX + ccc];
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(lok ? ya : 0.0, cc < LN ? xb : 0.0, d, 0, 0, 0);
             }
+            eacc[q] = d;
         }
     }
-    if (PAIRS) {
+    // row of `partial`: entry (l, s, c) at (l N + s) L + c
 #pragma unroll
-        for (int q = 0; q < LP_PB; ++q) {
-            const int b = tid + q * (int)blockDim.x;
-            if (b >= nblk) break;
-            const int l = 2 * (b % NH), cs = 2 * (b / NH);
+    for (int q = 0; q < LP_MAXB; ++q) {
+        const int cb = wave + q * nw;
+        if (cb >= NB) break;
+        const int cs = cb * 16 + lr;
+        if (cs >= LN) continue;
+        const int c = cs / N, s = cs - c * N;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int le = l + (e >> 1), cse = cs + (e & 1);
-                const int c = cse / N, s = cse % N;
-                partial[(size_t)blockIdx.x * nU + (le * N + s) * L + c] = pacc[4 * q + e];
-            }
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < LP_UPT; ++q) {
-            const int u = tid + q * (int)blockDim.x;
-            if (u < nU) partial[(size_t)blockIdx.x * nU + u] = pacc[q];
+        for (int i = 0; i < 4; ++i) {
+            const int l = 4 * i + lk;
+            if (l < N) partial[(size_t)blockIdx.x * (N * LN) + (l * N + s) * L + c] = eacc[q][i];
         }
     }
 }
@@ -562,8 +541,11 @@ template <int N>
 void launch_lastprod_n(const LastProdParams &p, const double *X, const double *Y, const double *U, double *out,
                        double *Ubar, double *partial, hipStream_t s) {
     const uint32_t nb = p.n_o1 * p.n_o2;
-    const size_t lds = sizeof(double) * ((size_t)N * N * p.L + (size_t)LP_JT * p.L * N + (size_t)LP_JT * N) +
+    const size_t lds = sizeof(double) * ((size_t)(N + LP_JT) * lp_stride(p.L, N) + (size_t)LP_JT * N) +
                        sizeof(uint32_t) * ((size_t)LP_MAXL + (size_t)LP_JT * N);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)lastprod_adjoint_kernel<N>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
     lastprod_adjoint_kernel<N><<<nb, kT, lds, s>>>(p, X, Y, U, out, partial);
     const int nU = N * N * p.L;
     double *part2 = partial + (size_t)nb * nU;  // LP_G rows after the per-workgroup ones
