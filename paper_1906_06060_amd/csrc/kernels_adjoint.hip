@@ -384,12 +384,12 @@ typedef double lp_dbl4 __attribute__((ext_vector_type(4)));
 __host__ __device__ inline int lp_stride(int L, int N) { return (L * N + 3) / 4 * 4 + 1; }
 }  // namespace
 
+// (four waves per SIMD: four workgroups per CU, so the usual 1000-workgroup
+// grid of one slice runs in one round)
 template <int N>
-__global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, const double *__restrict__ X,
-                                                              const double *__restrict__ Y,
-                                                              const double *__restrict__ U,
-                                                              double *__restrict__ out,
-                                                              double *__restrict__ partial) {
+__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4)))
+lastprod_adjoint_kernel(LastProdParams p, const double *__restrict__ X, const double *__restrict__ Y,
+                        const double *__restrict__ U, double *__restrict__ out, double *__restrict__ partial) {
     static_assert(N <= 16, "one 16-wide block of l");
     extern __shared__ __align__(16) double lp_sm[];
     const int L = p.L, LN = L * N;
@@ -423,35 +423,86 @@ __global__ void __launch_bounds__(kT) lastprod_adjoint_kernel(LastProdParams p, 
     const int lrc = lok ? lr : N - 1;
     if (p.cls)
         for (int c = tid; c < L; c += blockDim.x) sRt[c] = p.rtab[(o1 * p.x_o1 + c * p.xc) / p.ks.d];
+    // tile entries (jj, cs) of this thread: tid, tid + kT, ... walked
+    // incrementally; every load of a stage is issued before the first LDS
+    // store, so their latencies overlap (the stage is latency-bound)
+    constexpr int XB = 8;
+    constexpr int YIT = (LP_JT * N + kT - 1) / kT;
+    const int nxit = (LP_JT * LN + kT - 1) / kT;  // entries per thread and tile
+    const int jj0 = tid / LN, cs0 = tid - jj0 * LN, djj = kT / LN, dcs = kT - djj * LN;
+    // class blocks selected without indexing the parameter arrays by a lane
+    // value (which would read them from memory for every entry)
+    const double *__restrict__ blk0 = p.blk[0], *__restrict__ blk1 = p.blk[1];
+    const uint32_t ldb0 = p.ldb[0], ldb1 = p.ldb[1];
     for (uint32_t j0 = 0; j0 < p.NJ; j0 += LP_JT) {
         __syncthreads();  // previous tile consumed (and sU staged on the first pass)
-        if (p.cls) {
-            for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
-                const int s = idx % N, jj = idx / N;
+        {   // Y tile and, for class blocks, the K table entries of the tile
+            double yv[YIT];
+            uint32_t kv[YIT];
+#pragma unroll
+            for (int it = 0; it < YIT; ++it) {
+                const int idx = tid + it * kT, jj = idx / N, l = idx - jj * N;
                 const uint32_t j = j0 + jj;
-                sKt[idx] = j < p.NJ ? p.ktab[o2 * p.x_o2 + j * p.xj + s * p.xs] : 0u;
+                const bool ok = idx < LP_JT * N && j < p.NJ;
+                yv[it] = ok ? Y[oo + j * p.oj + l * p.ol] : 0.0;
+                kv[it] = ok && p.cls ? p.ktab[o2 * p.x_o2 + j * p.xj + l * p.xs] : 0u;
             }
-            __syncthreads();
-        }
-        for (int idx = tid; idx < LP_JT * LN; idx += blockDim.x) {
-            const int cs = idx % LN, jj = idx / LN, c = cs / N, s = cs - c * N;
-            const uint32_t j = j0 + jj;
-            double v = 0.0;
-            if (j < p.NJ) {
-                if (p.cls) {
-                    const uint32_t kt = sKt[jj * N + s], rt = sRt[c], b = kt >> 31;
-                    if ((rt >> 31) == (b ^ p.zs))
-                        v = p.blk[b][(size_t)(rt & ~Z2_PAR) * p.ldb[b] + (kt & ~Z2_PAR)];
-                } else {
-                    v = X[xo + j * p.xj + c * p.xc + s * p.xs];
+#pragma unroll
+            for (int it = 0; it < YIT; ++it) {
+                const int idx = tid + it * kT;
+                if (idx < LP_JT * N) {
+                    sY[idx] = yv[it];
+                    sKt[idx] = kv[it];
                 }
             }
-            sX[jj * SX + cs] = v;
         }
-        for (int idx = tid; idx < LP_JT * N; idx += blockDim.x) {
-            const int l = idx % N, jj = idx / N;
-            const uint32_t j = j0 + jj;
-            sY[idx] = j < p.NJ ? Y[oo + j * p.oj + l * p.ol] : 0.0;
+        if (p.cls) __syncthreads();
+        {   // X tile, in batches of XB loads in flight per thread: every lane
+            // loads (entries that are zero or outside the tile read U[0]
+            // instead) and the selection happens at the LDS store, so no load
+            // waits on a divergent branch
+            int jj = jj0, cs = cs0;
+            for (int it0 = 0; it0 < nxit; it0 += XB) {
+                double xv[XB];
+                uint32_t use = 0;
+                int sj = jj, sc = cs;
+#pragma unroll
+                for (int it = 0; it < XB; ++it) {
+                    const double *src = U;
+                    const uint32_t j = j0 + jj;
+                    if (jj < LP_JT && j < p.NJ) {
+                        const int c = cs / N, s = cs - c * N;
+                        if (p.cls) {
+                            const uint32_t kt = sKt[jj * N + s], rt = sRt[c], b = kt >> 31;
+                            if ((rt >> 31) == (b ^ p.zs)) {
+                                src = (b ? blk1 : blk0) + ((size_t)(rt & ~Z2_PAR) * (b ? ldb1 : ldb0) +
+                                                           (kt & ~Z2_PAR));
+                                use |= 1u << it;
+                            }
+                        } else {
+                            src = X + (xo + j * p.xj + c * p.xc + s * p.xs);
+                            use |= 1u << it;
+                        }
+                    }
+                    xv[it] = *src;
+                    cs += dcs;
+                    jj += djj;
+                    if (cs >= LN) {
+                        cs -= LN;
+                        ++jj;
+                    }
+                }
+#pragma unroll
+                for (int it = 0; it < XB; ++it) {
+                    if (sj < LP_JT) sX[sj * SX + sc] = (use >> it) & 1u ? xv[it] : 0.0;
+                    sc += dcs;
+                    sj += djj;
+                    if (sc >= LN) {
+                        sc -= LN;
+                        ++sj;
+                    }
+                }
+            }
         }
         __syncthreads();
         // outputs: one 16 j x 16 l block per wave (rows past NJ and columns
