@@ -26,7 +26,7 @@ PEAK_FP64 = 78.6e12    # MI355X FP64 matrix, flop/s
 # HBM bytes per GEMM call (main + tail dispatch + fix-up) of the bf16x3 GEMM at this workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # plain 2 GiB copy); valid only while the kernel source is the one profiled.
-GEMM_TRAFFIC_BYTES = {("z2", 10, True, True): 72359328728}
+GEMM_TRAFFIC_BYTES = {("z2", 10, True, True): 71635075814}
 GEMM_TRAFFIC_SRC_SHA = "5564fef28b45ecad"
 
 
