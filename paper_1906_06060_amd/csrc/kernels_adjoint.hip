@@ -363,9 +363,10 @@ bool launch_xmv(const XmvParams &p, const double *X, const double *Y, double *ou
 //   isometry   E[l, cs] += sum_j Y[j, l] X[j, cs]      (16 l x 16 cs blocks,
 //              accumulated over the tiles in the matrix registers);
 // at the end the workgroup stores E as one row of `partial`.  The products
-// take a small part of the time; the kernel is bound by the gather of X
-// (through the class tables in the block form), which the element-wise form
-// of the same sums (three LDS operands per four FMAs) had hidden only in part.
+// take a small part of the time (the element-wise form of the same sums, three
+// LDS operands per four FMAs, was about 1.5% slower in the whole reverse
+// pass); the kernel is bound by the gather of X, through the class tables in
+// the block form.
 // MFMA operand layout (16 x 4 A, 4 x 16 B, 16 x 16 D): lane t
 // supplies A[t % 16][t / 16] and B[t / 16][t % 16], and holds D[4 i + t / 16]
 // [t % 16] in its register i.
